@@ -1,0 +1,310 @@
+"""Pins of the CPU oracle against what the paper and mathematics fix.
+
+Every test here runs on the CPU.  None compares the oracle with a retyped
+copy of itself: each check comes from a closed form, a combinatorial
+identity, an independent brute force, or an equation or matrix printed in
+the paper.
+"""
+import os
+from math import comb
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1911_10616_amd import graphgen as gg
+from tests import bruteforce as bf
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _load_matrix(name):
+    rows = []
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                rows.append([int(x) for x in line.split()])
+    return np.array(rows, np.int64)
+
+
+# ---------------------------------------------------------------- tables
+
+def test_tables_consistent():
+    assert oracle.tables_status() == 0
+    t = oracle.tables()
+    # every orbit 0..72 in exactly one pattern, sizes add up to the pattern size
+    assert sorted(set(t["orbit_graphlet"].tolist())) == list(range(30))
+    for h in range(30):
+        k = t["pattern_k"][h]
+        orbs = set(t["node_orbit"][h][:k].tolist())
+        assert sum(t["orbit_size"][o] for o in orbs) == k
+
+
+def test_every_connected_labelled_graph_once():
+    # number of connected labelled graphs on k vertices: 1, 4, 38, 728
+    # (a classical count) -- so the 30 transcribed patterns are exactly the
+    # connected graphs on 2..5 vertices, each once up to isomorphism.
+    t = oracle.tables()
+    for k, expect in ((2, 1), (3, 4), (4, 38), (5, 728)):
+        got = sum(1 for mask in range(1 << comb(k, 2)) if oracle.classify_mask(k, mask)[0] >= 0)
+        assert got == expect
+        # orbit-stabiliser: each pattern appears k!/|Aut| times
+        import math
+        s = sum(math.factorial(k) // int(t["aut"][h]) for h in range(30) if t["pattern_k"][h] == k)
+        assert s == expect
+
+
+def test_tables_match_independent_transcription():
+    po = bf.pattern_orbits()
+    t = oracle.tables()
+    for h, (k, es, orbit, naut) in enumerate(po):
+        assert t["pattern_k"][h] == k
+        assert t["aut"][h] == naut
+        assert sorted(t["node_orbit"][h][:k].tolist()) == sorted(orbit)
+
+
+def test_named_orbits():
+    # Introduction: orbit 17 = middle of a 4-path (H9), 15 = its ends,
+    # 34 = the 5-cycle; orbit 70 (H28, clique minus an edge) = the two
+    # non-adjacent vertices.
+    rp, ci = gg.path(5)
+    c = oracle.induced_counts(rp, ci)
+    assert c[2, 17] == 1 and c[0, 15] == 1 and c[4, 15] == 1 and c[1, 16] == 1
+    rp, ci = gg.cycle(5)
+    assert (oracle.induced_counts(rp, ci)[:, 34] == 1).all()
+    e = [(i, j) for i in range(5) for j in range(i + 1, 5) if (i, j) != (0, 4)]
+    rp, ci = gg.from_edge_list(5, e)
+    c = oracle.induced_counts(rp, ci)
+    assert c[0, 70] == 1 and c[4, 70] == 1 and (c[1:4, 71] == 1).all()
+
+
+# ---------------------------------------------------------- closed forms
+
+def _only(row, expect):
+    got = {int(i): int(row[i]) for i in np.nonzero(row)[0]}
+    exp = {k: v for k, v in expect.items() if v}
+    assert got == exp, (got, exp)
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 5, 6, 7, 9])
+def test_complete_graph(n):
+    rp, ci = gg.complete(n)
+    c = oracle.induced_counts(rp, ci)
+    for u in range(n):
+        _only(c[u], {0: n - 1, 3: comb(n - 1, 2), 14: comb(n - 1, 3), 72: comb(n - 1, 4)})
+
+
+@pytest.mark.parametrize("n", [3, 4, 5, 6, 7, 11])
+def test_cycle(n):
+    rp, ci = gg.cycle(n)
+    c = oracle.induced_counts(rp, ci)
+    if n == 3:
+        e = {0: 2, 3: 1}
+    elif n == 4:
+        e = {0: 2, 1: 2, 2: 1, 8: 1}
+    elif n == 5:
+        e = {0: 2, 1: 2, 2: 1, 4: 2, 5: 2, 34: 1}
+    else:
+        e = {0: 2, 1: 2, 2: 1, 4: 2, 5: 2, 15: 2, 16: 2, 17: 1}
+    for u in range(n):
+        _only(c[u], e)
+
+
+@pytest.mark.parametrize("s", [1, 2, 3, 4, 6, 9])
+def test_star(s):
+    rp, ci = gg.star(s)
+    c = oracle.induced_counts(rp, ci)
+    _only(c[0], {0: s, 2: comb(s, 2), 7: comb(s, 3), 23: comb(s, 4)})
+    for u in range(1, s + 1):
+        _only(c[u], {0: 1, 1: s - 1, 6: comb(s - 1, 2), 22: comb(s - 1, 3)})
+
+
+@pytest.mark.parametrize("a,b", [(2, 2), (2, 3), (3, 3), (3, 5), (4, 6)])
+def test_complete_bipartite(a, b):
+    rp, ci = gg.complete_bipartite(a, b)
+    c = oracle.induced_counts(rp, ci)
+
+    def side(x, y):  # vertex on the side of size x, degree y
+        return {0: y, 1: y * (x - 1), 2: comb(y, 2), 6: y * comb(x - 1, 2), 7: comb(y, 3),
+                8: (x - 1) * comb(y, 2), 22: y * comb(x - 1, 3), 23: comb(y, 4),
+                49: comb(x - 1, 2) * comb(y, 2), 50: (x - 1) * comb(y, 3)}
+    for u in range(a):
+        _only(c[u], side(a, b))
+    for u in range(a, a + b):
+        _only(c[u], side(b, a))
+
+
+# ------------------------------------------------------------ invariants
+
+def _invariants(rp, ci, c):
+    t = oracle.tables()
+    deg = np.diff(rp.astype(np.int64))
+    assert (c[:, 0].astype(np.int64) == deg).all()
+    tot = c.astype(object).sum(axis=0)
+    for h in range(30):
+        orbs = sorted(set(t["node_orbit"][h][:t["pattern_k"][h]].tolist()))
+        copies = {int(tot[o]) // int(t["orbit_size"][o]) for o in orbs}
+        for o in orbs:
+            assert int(tot[o]) % int(t["orbit_size"][o]) == 0
+        assert len(copies) == 1, (h, copies)
+    # triangle total: trace(A^3)/6
+    n = len(rp) - 1
+    A = np.zeros((n, n), np.int64)
+    for u in range(n):
+        A[u, ci[rp[u]:rp[u + 1]]] = 1
+    assert int(tot[3]) // 3 == int(np.trace(A @ A @ A)) // 6
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_invariants_random(seed):
+    rp, ci = gg.erdos_renyi(40, 0.12, seed)
+    _invariants(rp, ci, oracle.induced_counts(rp, ci))
+
+
+def test_invariants_barabasi_albert():
+    rp, ci = gg.barabasi_albert(60, 3, 7)
+    _invariants(rp, ci, oracle.induced_counts(rp, ci))
+
+
+# ---------------------------------------------- independent brute force
+
+@pytest.mark.parametrize("seed", range(6))
+def test_brute_force_induced(seed):
+    n = 7 + seed % 2
+    rp, ci = gg.erdos_renyi(n, 0.45, 100 + seed)
+    np.testing.assert_array_equal(oracle.induced_counts(rp, ci).astype(np.int64),
+                                  bf.induced(rp, ci))
+
+
+def test_brute_force_all_graphs_on_5_vertices():
+    pairs = [(i, j) for i in range(5) for j in range(i + 1, 5)]
+    for mask in range(0, 1 << 10, 3):  # every third labelled graph (342)
+        e = [pairs[b] for b in range(10) if mask >> b & 1]
+        rp, ci = gg.from_edge_list(5, e)
+        np.testing.assert_array_equal(oracle.induced_counts(rp, ci).astype(np.int64),
+                                      bf.induced(rp, ci))
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_brute_force_noninduced(seed):
+    rp, ci = gg.erdos_renyi(7, 0.5, 200 + seed)
+    np.testing.assert_array_equal(oracle.noninduced_counts(rp, ci).astype(np.int64),
+                                  bf.noninduced(rp, ci))
+
+
+def test_two_modes_agree_with_transform():
+    A = oracle.transform_matrix()
+    for seed in range(3):
+        rp, ci = gg.erdos_renyi(14, 0.35, 300 + seed)
+        I = oracle.induced_counts(rp, ci).astype(np.int64)
+        N = oracle.noninduced_counts(rp, ci).astype(np.int64)
+        np.testing.assert_array_equal(I @ A.T, N)
+
+
+def test_rooted_matches_full():
+    rp, ci = gg.erdos_renyi(50, 0.1, 5)
+    full = oracle.induced_counts(rp, ci, threads=4)
+    roots = np.array([0, 3, 17, 49, 22], np.uint32)
+    r, comp = oracle.rooted_counts(rp, ci, roots, threads=2)
+    assert comp.all()
+    np.testing.assert_array_equal(r, full[roots])
+    r2, comp2 = oracle.rooted_counts(rp, ci, roots, budget=5)
+    assert not comp2.any()
+
+
+def test_threads_agree():
+    rp, ci = gg.erdos_renyi(80, 0.08, 9)
+    np.testing.assert_array_equal(oracle.induced_counts(rp, ci, threads=1),
+                                  oracle.induced_counts(rp, ci, threads=4))
+
+
+# ----------------------------------------- paper's equations and Fig. A
+
+def _basic(rp, ci):
+    adj = bf.adjacency_sets(rp, ci)
+    n = len(adj)
+    d = np.array([len(a) for a in adj], np.int64)
+    T = {}
+    for u in range(n):
+        for v in adj[u]:
+            T[(u, v)] = len(adj[u] & adj[v])
+    Tv = np.array([sum(T[(u, v)] for v in adj[u]) // 2 for u in range(n)], np.int64)
+    return adj, d, T, Tv
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_lemma_4vertex_equations(seed):
+    """Lemma 4vertexorbit: non-induced counts of orbits 1..13 from degrees
+    and triangle counts (8 and 14 need 4-cycles / 4-cliques, checked by the
+    brute-force test above)."""
+    rp, ci = gg.erdos_renyi(16, 0.3, 400 + seed)
+    N = oracle.noninduced_counts(rp, ci).astype(np.int64)
+    adj, d, T, Tv = _basic(rp, ci)
+    for u in range(len(adj)):
+        Nu = adj[u]
+        n1 = sum(d[v] - 1 for v in Nu)
+        n1v = {v: sum(d[x] - 1 for x in adj[v]) for v in Nu}
+        assert N[u, 0] == d[u]
+        assert N[u, 1] == n1
+        assert N[u, 2] == comb(d[u], 2)
+        assert N[u, 3] == Tv[u]
+        assert N[u, 4] == sum(n1v.values()) - 2 * comb(d[u], 2) - 2 * Tv[u]
+        assert N[u, 5] == n1 * (d[u] - 1) - 2 * Tv[u]
+        assert N[u, 6] == sum(comb(d[v] - 1, 2) for v in Nu)
+        assert N[u, 7] == comb(d[u], 3)
+        assert N[u, 9] == sum(Tv[v] - T[(u, v)] for v in Nu)
+        assert N[u, 10] == sum(T[(u, v)] * (d[v] - 2) for v in Nu)
+        assert N[u, 11] == Tv[u] * (d[u] - 2)
+        tri = [(v, x) for v in Nu for x in Nu if v < x and x in adj[v]]
+        assert N[u, 12] == sum(T[(v, x)] - 1 for v, x in tri)
+        assert N[u, 13] == sum(comb(T[(u, v)], 2) for v in Nu)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_worked_example_orbit26(seed):
+    """Equation (orb26), the paper's worked example of the cutting lemma:
+    DM(u, 26) = sum over triangles {u,v,w} of (d(u)-2)((d(v)-2)+(d(w)-2))
+    minus 2 DM(u, 13)."""
+    rp, ci = gg.erdos_renyi(18, 0.3, 500 + seed)
+    N = oracle.noninduced_counts(rp, ci).astype(np.int64)
+    adj, d, T, Tv = _basic(rp, ci)
+    for u in range(len(adj)):
+        tri = [(v, w) for v in adj[u] for w in adj[u] if v < w and w in adj[v]]
+        s = sum((d[u] - 2) * ((d[v] - 2) + (d[w] - 2)) for v, w in tri)
+        assert N[u, 26] == s - 2 * N[u, 13]
+
+
+def test_fig_A_four_vertex_block():
+    A = oracle.transform_matrix()
+    fig = _load_matrix("fig_A_4vertex.txt")
+    fixed = fig.copy()
+    fixed[5 - 4, 13 - 4] = 4  # erratum, reason in the fixture header
+    np.testing.assert_array_equal(A[4:15, 4:15], fixed)
+    # the only disagreement with the printed figure is that one entry
+    diff = np.argwhere(A[4:15, 4:15] != fig)
+    assert diff.tolist() == [[1, 9]]
+    Ainv = np.round(np.linalg.inv(A[4:15, 4:15].astype(float))).astype(np.int64)
+    figinv = _load_matrix("fig_Ainv_4vertex.txt")
+    rows = [i for i in range(11) if i != 1]
+    np.testing.assert_array_equal(Ainv[rows], figinv[rows])
+
+
+def test_transform_structure():
+    """A is block-diagonal by pattern size, unit upper-triangular in the
+    paper's orbit order, and its entries obey Moebius inversion over edge
+    subsets: A^-1[i,j] = (-1)^(e(H_j) - e(H_i)) A[i,j]."""
+    A = oracle.transform_matrix()
+    t = oracle.tables()
+    size = lambda o: int(t["pattern_k"][t["orbit_graphlet"][o]])
+    for i in range(73):
+        for j in range(73):
+            if size(i) != size(j):
+                assert A[i, j] == 0
+        assert A[i, i] == 1
+    assert np.all(np.tril(A, -1) == 0)
+    ne = {h: len(bf.PATTERNS[h][0].split()) for h in range(30)}
+    e = np.array([ne[int(t["orbit_graphlet"][o])] for o in range(73)])
+    sign = (-1) ** ((e[None, :] - e[:, None]) % 2)
+    Ainv = sign * A
+    np.testing.assert_array_equal(A @ Ainv, np.eye(73, dtype=np.int64))
