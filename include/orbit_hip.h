@@ -1,0 +1,114 @@
+/*
+ * orbit_hip.h -- C ABI of liborbit_hip.so: exact per-vertex orbit counts of
+ * all connected patterns with 2..5 vertices (orbits 0..72) on an AMD
+ * Instinct MI355X (gfx950), computed by the EVOKE method of Pashanasangi and
+ * Seshadhri ("Efficiently Counting Vertex Orbits of All 5-vertex Subgraphs,
+ * by EVOKE").
+ *
+ * Pipeline (all steps run in the library's own HIP kernels):
+ *   1. validate the CSR and compute degrees;
+ *   2. orient the graph into a DAG by a degeneracy order (bucketed k-core
+ *      peeling on the GPU; section "Preliminaries", degree-ordering
+ *      paragraph, uses a degree order -- any total order gives the same
+ *      counts, it only changes the work);
+ *   3. enumerate directed triangles, 4-cycles, 4-/5-cliques, wedges,
+ *      diamonds and directed 3-paths (Fig. 5vertex-basis; Theorem 4orbit;
+ *      Theorem on 5-cycle/5-clique running time);
+ *   4. combine them through the orbit equations (Lemma 4vertexorbit,
+ *      Lemma 4edgeorbit, Theorem 5vertexorbit) into non-induced counts;
+ *   5. convert to induced counts with the exact integer inverse of the
+ *      transform of appendix "Conversion between Induced and Noninduced
+ *      counts".
+ *
+ * Conventions shared by every entry point
+ *   - Graph: simple undirected graph as a symmetric CSR.  row_ptr has n+1
+ *     uint32 entries, row_ptr[0] == 0, row_ptr[n] == 2m; col_idx has 2m
+ *     uint32 entries; each neighbour list strictly ascending; no self-loops;
+ *     every edge stored in both directions; 2m < 2^32.  Isolated vertices
+ *     are allowed.  The input is always validated; a malformed graph is
+ *     rejected with an error code before any counting kernel runs.
+ *   - Output: counts[u * K + o], uint64, K = orbit_num_orbits(k_max)
+ *     (4 for k_max = 3, 15 for k_max = 4, 73 for k_max = 5).  Induced
+ *     counts by default (the paper's problem statement asks for induced
+ *     counts); ORB_NONINDUCED returns the non-induced counts DM(u, theta)
+ *     of Definition unlabeled-match.  Values are exact modulo 2^64 (all
+ *     arithmetic wraps; binomials are formed exactly before reduction).
+ *   - Pointers: row_ptr, col_idx, counts and workspace are DEVICE pointers
+ *     owned by the caller; the library never frees them.  `stream` is a
+ *     hipStream_t (NULL = the null stream).
+ *   - Errors: an int status, 0 on success, negative ORB_E_* otherwise; never
+ *     throws across the ABI, never aborts.  On error the contents of counts
+ *     are unspecified.
+ *   - Synchronisation: the calls return after the work has finished on the
+ *     stream (they read a few status words back from the device).
+ *   - Thread safety: calls on different streams/devices may run concurrently;
+ *     each call uses only its own workspace.
+ */
+#ifndef ORBIT_HIP_H
+#define ORBIT_HIP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define ORB_OK 0
+#define ORB_E_INVALID_ARG (-1)  /* bad n/m/k_max/pointer/flags */
+#define ORB_E_NOT_SORTED (-2)   /* a neighbour list is not ascending */
+#define ORB_E_SELF_LOOP (-3)
+#define ORB_E_DUPLICATE (-4)    /* an edge appears twice in a list */
+#define ORB_E_ASYMMETRIC (-5)   /* (u,v) present but (v,u) missing */
+#define ORB_E_OUT_OF_RANGE (-6) /* col_idx >= n, or row_ptr not monotone / not ending at 2m */
+#define ORB_E_WORKSPACE (-7)    /* workspace too small: see *ws_required */
+#define ORB_E_DEVICE (-8)       /* a HIP call failed */
+#define ORB_E_INTERNAL (-9)     /* internal consistency check failed */
+
+/* option flags */
+#define ORB_NONINDUCED 0x1u /* return non-induced counts DM(u, theta) */
+#define ORB_TIMING 0x2u     /* record per-phase times (orbit_last_phase_times) */
+
+typedef struct orb_opts {
+    uint32_t flags;     /* ORB_* option bits */
+    uint32_t num_wg;    /* persistent workgroups for the per-source kernels; 0 = default */
+} orb_opts;
+
+/* Number of output columns K for k_max (3, 4 or 5); 0 if k_max is invalid. */
+int orbit_num_orbits(int k_max);
+
+/* Minimal form: counts for every vertex, default options, null stream.
+ * Allocates its workspace with hipMalloc and frees it before returning.
+ * m = number of undirected edges (col_idx has 2m entries). */
+int orbit_count(const uint32_t *row_ptr, const uint32_t *col_idx, uint32_t n, uint64_t m,
+                int k_max, uint64_t *counts);
+
+/* Workspace size that orbit_count_ex needs for this graph.  The size
+ * depends on the number of triangles, so this call validates the graph,
+ * orients it and counts triangles on the device (allocating and freeing
+ * its own temporary memory) before returning the size in *bytes. */
+int orbit_workspace_query(const uint32_t *row_ptr, const uint32_t *col_idx, uint32_t n,
+                          uint64_t m, int k_max, void *stream, const orb_opts *opts,
+                          uint64_t *bytes);
+
+/* Full form: uses only the caller's workspace (device memory of ws_bytes
+ * bytes, 256-byte aligned); allocates no device memory.  If the workspace
+ * is too small it returns ORB_E_WORKSPACE and, when ws_required is not
+ * NULL, stores the size it needs there.  opts may be NULL. */
+int orbit_count_ex(const uint32_t *row_ptr, const uint32_t *col_idx, uint32_t n, uint64_t m,
+                   int k_max, uint64_t *counts, void *workspace, uint64_t ws_bytes,
+                   uint64_t *ws_required, void *stream, const orb_opts *opts);
+
+/* Human-readable text of a status code (static storage). */
+const char *orbit_strerror(int status);
+
+/* Per-phase GPU times (ms) of the calling thread's last orbit_count_ex with
+ * ORB_TIMING: writes up to max_phases values and their names (static
+ * strings) and returns the number of phases. */
+int orbit_last_phase_times(float *ms, const char **names, int max_phases);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ORBIT_HIP_H */

@@ -1,0 +1,267 @@
+// Per-vertex kernels: neighbour sums, the triangle sweep, the orbit
+// equations of Lemma 4vertexorbit and Theorem 5vertexorbit, and the
+// non-induced -> induced transform.
+#include "orbit_common.h"
+#include "orbit_tables.h"
+
+#define NI(u, o) ni[(u64)(u) * ORB_NORB + (o)]
+
+// Tv(u) = number of triangles at u (half the sum of T over u's edges);
+// N1(u) = sum over neighbours v of (d(v) - 1) (orbit 1).
+__global__ void k_vert0(const u32 *rp, const u32 *ci, const u32 *deg, const u32 *T, u32 n,
+                        u64 *Tv, u64 *N1) {
+    for (u64 u = GWAVE; u < n; u += NWAVES) {
+        u64 t = 0, n1 = 0;
+        for (u32 s = rp[u] + lane_id(); s < rp[u + 1]; s += WAVE) {
+            t += T[s];
+            n1 += (u64)deg[ci[s]] - 1;
+        }
+        t = wave_sum_u64(t);
+        n1 = wave_sum_u64(n1);
+        if (lane_id() == 0) { Tv[u] = t / 2; N1[u] = n1; }
+    }
+}
+
+// Triangle sweep: for every triangle {u,v,x} at u, the summands of the
+// orbit equations that sum over triangles (Lemma 4vertexorbit orbit 12;
+// Theorem 5vertexorbit orbits 25, 26, 29, 32, 43, 46, 48, 52, 53, 54, 59,
+// 61, 65).  Each triangle is visited from the slot (u,v) with v < x.
+__global__ void k_trisweep(const u32 *rp, const u32 *ci, const u32 *src, const u32 *rev,
+                           const u32 *deg, const u32 *T, const u64 *tl_ptr, const uint2 *tl,
+                           const u64 *Tv, const u64 *N1, const u64 *E7, const u64 *E9,
+                           const u64 *C4e, const u64 *K4e, u32 n, u64 *ni) {
+    for (u64 u = GWAVE; u < n; u += NWAVES) {
+        u64 a12 = 0, a25 = 0, a26 = 0, a29 = 0, a32 = 0, a43 = 0, a46 = 0, a48 = 0, a52 = 0,
+            a53 = 0, a54 = 0, a59 = 0, a61 = 0, a65 = 0;
+        const u64 du = deg[u];
+        for (u32 s = rp[u] + lane_id(); s < rp[u + 1]; s += WAVE) {
+            const u32 v = ci[s];
+            const u32 tuv = T[s];
+            if (tuv == 0) continue;
+            const bool lo = (u32)u < v;
+            const uint2 *p = tl + tl_ptr[lo ? s : rev[s]];
+            const u64 dv = deg[v];
+            const u64 c4uv = C4e[s];
+            for (u32 k = 0; k < tuv; k++) {
+                uint2 e = p[k];
+                const u32 sux = lo ? e.x : e.y, svx = lo ? e.y : e.x;
+                const u32 x = ci[sux];
+                if (x < v) continue;
+                const u32 sxv = rev[svx];
+                const u64 dx = deg[x];
+                const u64 tvx = T[svx], tux = T[sux];
+                a12 += tvx - 1;
+                a25 += (dv - 2) * (dx - 2);
+                a26 += (du - 2) * ((dv - 2) + (dx - 2));
+                a29 += N1[v] + N1[x];
+                a32 += c2((i64)dv - 2) + c2((i64)dx - 2);
+                a43 += (Tv[v] - 1) + (Tv[x] - 1);
+                a46 += E7[svx];
+                a48 += ((u64)tuv - 1) * (dx - 2) + (tux - 1) * (dv - 2);
+                a52 += C4e[svx];
+                a53 += c4uv + C4e[sux];
+                a54 += c2((i64)tvx - 1);
+                a59 += E9[sxv] + E9[svx];
+                a61 += ((u64)tuv - 1) * (tux - 1);
+                a65 += K4e[svx];
+            }
+        }
+        a12 = wave_sum_u64(a12); a25 = wave_sum_u64(a25); a26 = wave_sum_u64(a26);
+        a29 = wave_sum_u64(a29); a32 = wave_sum_u64(a32); a43 = wave_sum_u64(a43);
+        a46 = wave_sum_u64(a46); a48 = wave_sum_u64(a48); a52 = wave_sum_u64(a52);
+        a53 = wave_sum_u64(a53); a54 = wave_sum_u64(a54); a59 = wave_sum_u64(a59);
+        a61 = wave_sum_u64(a61); a65 = wave_sum_u64(a65);
+        if (lane_id() == 0) {
+            NI(u, 12) = a12; NI(u, 25) = a25; NI(u, 26) = a26; NI(u, 29) = a29;
+            NI(u, 32) = a32; NI(u, 43) = a43; NI(u, 46) = a46; NI(u, 48) = a48;
+            NI(u, 52) = a52; NI(u, 53) = a53; NI(u, 54) = a54; NI(u, 59) = a59;
+            NI(u, 61) = a61; NI(u, 65) = a65;
+        }
+    }
+}
+
+// First-order neighbour sums and the final orbits 0..14 (Lemma
+// 4vertexorbit).  Temporary sums that later equations need are parked in
+// the columns of the orbits they feed (28, 31, 37, 56, 60).  Orbit 69 of u
+// is half the sum, over arcs (v,u), of Q(v,u); the sum is even and is
+// accumulated in 128 bits so that the halving is exact modulo 2^64.
+__global__ void k_vert1(const u32 *rp, const u32 *ci, const u32 *rev, const u32 *deg,
+                        const u32 *T, const u64 *Tv, const u64 *N1, const u64 *C4v,
+                        const u64 *K4v, const u64 *C4e, const u64 *K4e, const u64 *E9,
+                        const u64 *Q, u32 n, u64 *ni) {
+    for (u64 u = GWAVE; u < n; u += NWAVES) {
+        const u64 du = deg[u];
+        u64 s4 = 0, n6 = 0, n9 = 0, n10 = 0, n13 = 0, s28 = 0, s31 = 0, n22 = 0, s37 = 0,
+            n40 = 0, n41 = 0, n55 = 0, s56 = 0, n57 = 0, s60 = 0, n67 = 0, qlo = 0, qhi = 0;
+        for (u32 s = rp[u] + lane_id(); s < rp[u + 1]; s += WAVE) {
+            const u32 v = ci[s];
+            const u64 dv = deg[v];
+            const u64 t = T[s];
+            const u32 r = rev[s];
+            const u64 tv = Tv[v];
+            s4 += N1[v];
+            n6 += c2((i64)dv - 1);
+            n9 += tv - t;
+            n10 += t * (dv - 2);
+            n13 += c2((i64)t);
+            s28 += tv;
+            s31 += (dv - 1) * tv;
+            n22 += c3((i64)dv - 1);
+            s37 += C4e[s] * (dv - 2);
+            n40 += E9[r] * (dv - 3);
+            n41 += c2((i64)t) * (dv - 3);
+            n55 += c3((i64)t);
+            s56 += K4v[v];
+            n57 += K4e[s] * (dv - 3);
+            s60 += E9[r] * (t - 1);
+            n67 += K4e[s] * (t - 2);
+            u64 q = Q[r];
+            qlo += q;
+            qhi += qlo < q;
+        }
+        s4 = wave_sum_u64(s4); n6 = wave_sum_u64(n6); n9 = wave_sum_u64(n9);
+        n10 = wave_sum_u64(n10); n13 = wave_sum_u64(n13); s28 = wave_sum_u64(s28);
+        s31 = wave_sum_u64(s31); n22 = wave_sum_u64(n22); s37 = wave_sum_u64(s37);
+        n40 = wave_sum_u64(n40); n41 = wave_sum_u64(n41); n55 = wave_sum_u64(n55);
+        s56 = wave_sum_u64(s56); n57 = wave_sum_u64(n57); s60 = wave_sum_u64(s60);
+        n67 = wave_sum_u64(n67);
+        // 128-bit sum of Q: add the lane partials pairwise with carries
+        for (int off = WAVE / 2; off > 0; off >>= 1) {
+            u64 olo = __shfl_xor(qlo, off, WAVE), ohi = __shfl_xor(qhi, off, WAVE);
+            u64 nlo = qlo + olo;
+            qhi = qhi + ohi + (nlo < qlo);
+            qlo = nlo;
+        }
+        if (lane_id() == 0) {
+            const u64 n1 = N1[u], t = Tv[u];
+            const u64 n2 = c2((i64)du), n3 = t;
+            NI(u, 0) = du;
+            NI(u, 1) = n1;
+            NI(u, 2) = n2;
+            NI(u, 3) = n3;
+            NI(u, 4) = s4 - 2 * n2 - 2 * n3;
+            NI(u, 5) = n1 * (du - 1) - 2 * n3;
+            NI(u, 6) = n6;
+            NI(u, 7) = c3((i64)du);
+            NI(u, 8) = C4v[u];
+            NI(u, 9) = n9;
+            NI(u, 10) = n10;
+            NI(u, 11) = t * (du - 2);
+            NI(u, 13) = n13;
+            NI(u, 14) = K4v[u];
+            NI(u, 22) = n22;
+            NI(u, 28) = s28;
+            NI(u, 31) = s31;
+            NI(u, 37) = s37;
+            NI(u, 40) = n40;
+            NI(u, 41) = n41;
+            NI(u, 55) = n55;
+            NI(u, 56) = s56;
+            NI(u, 57) = n57;
+            NI(u, 60) = s60;
+            NI(u, 67) = n67;
+            NI(u, 69) = (qlo >> 1) | (qhi << 63);
+        }
+    }
+}
+
+// Second-order neighbour sums and every remaining equation of Theorem
+// 5vertexorbit (with the corrected forms of orbits 19, 20, 21, 35, 40, 64,
+// 66, 68, 69 that the transcribed equations need), finishing the
+// non-induced counts of orbits 15..72 of u.  Reads only columns 4..13 of
+// the neighbours' rows, and writes only columns 15..72 of its own row.
+__global__ void k_vert2(const u32 *rp, const u32 *ci, const u32 *deg, const u64 *Tv,
+                        const u64 *N1, u32 n, u64 *ni) {
+    for (u64 u = GWAVE; u < n; u += NWAVES) {
+        u64 s15 = 0, s18 = 0, s19 = 0, s24 = 0, s27 = 0, s35 = 0, s39 = 0, s45 = 0;
+        for (u32 s = rp[u] + lane_id(); s < rp[u + 1]; s += WAVE) {
+            const u64 *r = ni + (u64)ci[s] * ORB_NORB;
+            s15 += r[4];
+            s19 += r[5];
+            s18 += r[6];
+            s35 += r[8];
+            s27 += r[9];
+            s24 += r[10];
+            s45 += r[12];
+            s39 += r[13];
+        }
+        s15 = wave_sum_u64(s15); s18 = wave_sum_u64(s18); s19 = wave_sum_u64(s19);
+        s24 = wave_sum_u64(s24); s27 = wave_sum_u64(s27); s35 = wave_sum_u64(s35);
+        s39 = wave_sum_u64(s39); s45 = wave_sum_u64(s45);
+        if (lane_id() != 0) continue;
+        u64 *R = ni + u * ORB_NORB;
+        const u64 d = deg[u];
+        const u64 n1 = N1[u], t = Tv[u];
+        const u64 n3 = R[3], n4 = R[4], n5 = R[5], n6 = R[6], n7 = R[7], n8 = R[8], n9 = R[9],
+                  n10 = R[10], n11 = R[11], n12 = R[12], n13 = R[13], n14 = R[14];
+        R[15] = s15 - n5 - 2 * n11 - 2 * n8;
+        R[16] = n4 * (d - 1) - n10 - 2 * n8;
+        R[17] = c2((i64)n1) - n3 - n6 - n8 - n10;
+        R[18] = s18 - 3 * n7 - n10;
+        R[19] = s19 - n4 - n5 - n10;
+        R[20] = (d - 1) * n6 - n10;
+        R[21] = c2((i64)d - 1) * n1 - 2 * n11;
+        // R[22] final from the first-order sums
+        R[23] = c4((i64)d);
+        R[24] = s24 - n10 - 2 * n11 - 2 * n12;
+        R[25] = R[25] - n12;
+        R[26] = R[26] - 2 * n13;
+        R[27] = s27 - n11 - 2 * n13;
+        R[28] = (d - 1) * R[28] - 2 * n3 - 2 * n11 - 2 * n12;
+        R[29] = R[29] - 4 * n3 - n10 - 2 * n11 - 2 * n12 - 2 * n13;
+        R[30] = t * n1 - 2 * n3 - n10 - 2 * n13;
+        R[31] = R[31] - 2 * n9 - n10 - 2 * n3;
+        // R[32] final from the triangle sweep
+        R[33] = t * c2((i64)d - 2);
+        // R[34] final from the 5-cycle kernel
+        R[35] = s35 - 2 * n8 - n13;
+        R[36] = R[36] - n13;
+        R[37] = R[37] - 2 * n12;
+        R[38] = n8 * (d - 2) - n13;
+        R[39] = s39 - n13 - 2 * n12;
+        // R[40], R[41] final from the first-order sums
+        R[42] = (d - 3) * n13;
+        R[43] = R[43] - 2 * n12 - 2 * n13;
+        R[44] = c2((i64)t) - n13;
+        R[45] = s45 - 2 * n13 - 3 * n14;
+        R[46] = R[46] - n11 - 3 * n14;
+        R[47] = n12 * (d - 2) - 3 * n14;
+        R[48] = R[48] - 6 * n14;
+        // R[49], R[50] final from the pair sweep
+        R[51] = R[51] - 2 * n12;
+        R[52] = R[52] - 2 * n13;
+        R[53] = R[53] - 2 * n13 - 2 * n12;
+        // R[54], R[55] final
+        R[56] = R[56] - 3 * n14;
+        // R[57] final
+        R[58] = n14 * (d - 3);
+        R[59] = R[59] - 2 * n13 - 6 * n14;
+        R[60] = R[60] - 6 * n14;
+        R[61] = R[61] - 3 * n14;
+        R[62] = R[62] - n13;
+        // R[63], R[64] final from the pair sweep
+        R[65] = R[65] - 3 * n14;
+        // R[66]..R[72] final (66, 71: triangle 4-clique terms; 67, 69:
+        // first-order sums; 68: wheel maps; 70, 72: clique passes)
+    }
+}
+
+// Induced counts: I = Ainv N per row, block by block; Ainv is unit upper
+// triangular, so row i only reads columns >= i and can be overwritten in
+// increasing order.  Writes the first K columns of every row to out (which
+// may alias ni when K == 73).
+__global__ void k_transform(u64 *ni, u32 n, int K, int induced, u64 *out) {
+    for (u64 u = GTID; u < n; u += GSTRIDE) {
+        u64 *R = ni + u * ORB_NORB;
+        if (induced) {
+            for (int i = 0; i < K; i++) {
+                u64 acc = 0;
+                for (int k = ORB_AINV_PTR[i]; k < ORB_AINV_PTR[i + 1]; k++)
+                    acc += (u64)(i64)ORB_AINV_VAL[k] * R[ORB_AINV_COL[k]];
+                R[i] = acc;
+            }
+        }
+        if (out != ni || K != ORB_NORB)
+            for (int i = 0; i < K; i++) out[u * K + i] = R[i];
+    }
+}

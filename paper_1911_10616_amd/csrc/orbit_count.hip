@@ -1,0 +1,818 @@
+// Enumeration kernels: directed triangles and per-edge triangle lists,
+// per-edge orbit quantities, 4-cycles, 4-/5-cliques, the pair sweep over
+// wedges and diamonds, and 5-cycles.
+#include "orbit_common.h"
+
+// Orbit columns written by these kernels (non-induced accumulators).
+#define NI(u, o) ni[(u64)(u) * ORB_NORB + (o)]
+
+// ======================================================= directed triangles
+// For every out-arc a->b (a before b in rank order) the common
+// out-neighbours c of a and b: each triangle a<b<c is found once, from its
+// two lowest-ranked vertices (the orientation of Fig. 5vertex-basis).
+__device__ inline u32 arc_owner_of(const u32 *src, const u32 *out_slot, u64 p) {
+    return src[out_slot[p]];
+}
+
+__global__ void k_tri_count(const u32 *src, const u64 *out_ptr, const u32 *out_nbr,
+                            const u32 *out_slot, u64 m, u32 *tcnt) {
+    for (u64 p = GTID; p < m; p += GSTRIDE) {
+        u32 a = arc_owner_of(src, out_slot, p), b = out_nbr[p];
+        u64 i = out_ptr[a], ie = out_ptr[a + 1], j = out_ptr[b], je = out_ptr[b + 1];
+        u32 c = 0;
+        while (i < ie && j < je) {
+            u32 x = out_nbr[i], y = out_nbr[j];
+            c += x == y;
+            i += x <= y;
+            j += y <= x;
+        }
+        tcnt[p] = c;
+    }
+}
+
+// Triangle records, grouped by owner arc (a->b) and sorted by c:
+// tri_c = c, tri_sab/sac/sbc = slots of (a,b), (a,c), (b,c).
+__global__ void k_tri_fill(const u32 *src, const u64 *out_ptr, const u32 *out_nbr,
+                           const u32 *out_slot, u64 m, const u64 *tri_ptr, u32 *tri_c,
+                           u32 *tri_sab, u32 *tri_sac, u32 *tri_sbc) {
+    for (u64 p = GTID; p < m; p += GSTRIDE) {
+        u32 a = arc_owner_of(src, out_slot, p), b = out_nbr[p];
+        u64 i = out_ptr[a], ie = out_ptr[a + 1], j = out_ptr[b], je = out_ptr[b + 1];
+        u64 w = tri_ptr[p];
+        u32 sab = out_slot[p];
+        while (i < ie && j < je) {
+            u32 x = out_nbr[i], y = out_nbr[j];
+            if (x == y) {
+                tri_c[w] = x;
+                tri_sab[w] = sab;
+                tri_sac[w] = out_slot[i];
+                tri_sbc[w] = out_slot[j];
+                w++;
+            }
+            i += x <= y;
+            j += y <= x;
+        }
+    }
+}
+
+// Per-slot triangle counts: T = all triangles on the edge, Tin = those
+// whose third vertex precedes both ends (|N-(x) & N-(y)|), Tmid (on the
+// slots of arc a->c) = those whose third vertex lies between (|N+(a) & N-(c)|).
+__global__ void k_tri_slots(const u32 *rev, u64 ntri, const u32 *tri_sab, const u32 *tri_sac,
+                            const u32 *tri_sbc, u32 *T, u32 *Tin, u32 *Tmid) {
+    for (u64 t = GTID; t < ntri; t += GSTRIDE) {
+        u32 sab = tri_sab[t], sac = tri_sac[t], sbc = tri_sbc[t];
+        atomicAdd(&T[sab], 1u); atomicAdd(&T[rev[sab]], 1u);
+        atomicAdd(&T[sac], 1u); atomicAdd(&T[rev[sac]], 1u);
+        atomicAdd(&T[sbc], 1u); atomicAdd(&T[rev[sbc]], 1u);
+        atomicAdd(&Tin[sbc], 1u); atomicAdd(&Tin[rev[sbc]], 1u);
+        atomicAdd(&Tmid[sac], 1u); atomicAdd(&Tmid[rev[sac]], 1u);
+    }
+}
+
+// Undirected per-edge triangle lists, stored once per edge at its canonical
+// slot (the slot in the list of the smaller id).  Entry for third vertex x
+// of edge (lo,hi): (slot of (lo,x), slot of (hi,x)).
+__device__ inline void tl_push(u32 s_xy, u32 s_xz, u32 s_yz, const u32 *src, const u32 *ci,
+                               const u32 *rev, const u64 *tl_ptr, u32 *tl_cur, uint2 *tl) {
+    // edge (x,y) with third vertex z; s_xz = slot (x,z), s_yz = slot (y,z)
+    u32 x = src[s_xy], y = ci[s_xy];
+    u32 cs = x < y ? s_xy : rev[s_xy];
+    uint2 e = x < y ? make_uint2(s_xz, s_yz) : make_uint2(s_yz, s_xz);
+    u32 pos = atomicAdd(&tl_cur[cs], 1u);
+    tl[tl_ptr[cs] + pos] = e;
+}
+
+__global__ void k_tl_fill(const u32 *src, const u32 *ci, const u32 *rev, u64 ntri,
+                          const u32 *tri_sab, const u32 *tri_sac, const u32 *tri_sbc,
+                          const u64 *tl_ptr, u32 *tl_cur, uint2 *tl) {
+    for (u64 t = GTID; t < ntri; t += GSTRIDE) {
+        u32 sab = tri_sab[t], sac = tri_sac[t], sbc = tri_sbc[t];
+        u32 sba = rev[sab], sca = rev[sac], scb = rev[sbc];
+        tl_push(sab, sac, sbc, src, ci, rev, tl_ptr, tl_cur, tl);  // edge ab, third c
+        tl_push(sac, sab, scb, src, ci, rev, tl_ptr, tl_cur, tl);  // edge ac, third b
+        tl_push(sbc, sba, sca, src, ci, rev, tl_ptr, tl_cur, tl);  // edge bc, third a
+    }
+}
+
+// Triangle list of slot s = (u,v) as (slot(u,x), slot(v,x)) pairs.
+struct TLView {
+    const uint2 *p;
+    u32 len;
+    bool swap;
+    __device__ inline uint2 get(u32 i) const {
+        uint2 e = p[i];
+        return swap ? make_uint2(e.y, e.x) : e;
+    }
+};
+__device__ inline TLView tl_view(u32 s, const u32 *src, const u32 *ci, const u32 *rev,
+                                 const u32 *T, const u64 *tl_ptr, const uint2 *tl) {
+    TLView v;
+    bool lo = src[s] < ci[s];
+    u32 cs = lo ? s : rev[s];
+    v.p = tl + tl_ptr[cs];
+    v.len = T[s];
+    v.swap = !lo;
+    return v;
+}
+
+// Edge orbits of Lemma 4edgeorbit that need the triangle list:
+// E7(u,v) = sum over triangles (u,v,x) of (d(x) - 2),
+// E9<u,v> = sum over triangles (u,v,x) of (T(u,x) - 1)   [at slot (u,v)].
+__global__ void k_edge_e7e9(const u32 *src, const u32 *ci, const u32 *rev, const u32 *deg,
+                            const u32 *T, const u64 *tl_ptr, const uint2 *tl, u64 M2, u64 *E7,
+                            u64 *E9) {
+    for (u64 s = GTID; s < M2; s += GSTRIDE) {
+        TLView v = tl_view((u32)s, src, ci, rev, T, tl_ptr, tl);
+        u64 e7 = 0, e9 = 0;
+        for (u32 i = 0; i < v.len; i++) {
+            uint2 e = v.get(i);
+            e7 += (u64)deg[ci[e.x]] - 2;
+            e9 += (u64)T[e.x] - 1;
+        }
+        E7[s] = e7;
+        E9[s] = e9;
+    }
+}
+
+// ======================================================= per-source kernels
+// One workgroup per source vertex at a time (dynamic), with dense per-WG
+// scratch arrays indexed by vertex id that are restored to zero after
+// every source.
+__device__ inline u32 next_source(u32 *counter, u32 *sh) {
+    __syncthreads();
+    if (threadIdx.x == 0) *sh = atomicAdd(counter, 1u);
+    __syncthreads();
+    return *sh;
+}
+
+// Dynamic loop of a wave over [0, count): items are taken from an LDS
+// counter, so a long item does not hold up the other waves' items.
+template <typename F>
+__device__ inline void wave_loop(u32 *counter, u32 count, F f) {
+    for (;;) {
+        u32 i = 0;
+        if (lane_id() == 0) i = atomicAdd(counter, 1u);
+        i = __shfl(i, 0, WAVE);
+        if (i >= count) break;
+        f(i);
+    }
+}
+
+__device__ inline u64 block_sum_u64(u64 v, u64 *sh) {
+    v = wave_sum_u64(v);
+    __syncthreads();
+    if (lane_id() == 0) sh[wave_in_wg()] = v;
+    __syncthreads();
+    u64 t = 0;
+    for (int w = 0; w < WAVES_PER_WG; w++) t += sh[w];
+    return t;
+}
+
+__device__ inline unsigned char *align256(unsigned char *p) {
+    return (unsigned char *)(((uintptr_t)p + 255) & ~(uintptr_t)255);
+}
+
+// ---- 4-cycles (Chiba-Nishizeki).  For every top vertex x: the wedges
+// x - y - z with y and z before x in rank order; cnt[z] = number of such y.
+// Every 4-cycle has a unique top x and opposite z; it adds C(cnt,2) to x and
+// z, cnt-1 to each middle y, and cnt-1 to the edges (x,y) and (y,z).
+// Gives C4(u) (orbit 8) and C4(e) (edge orbit E5).
+__global__ void __launch_bounds__(WG) k_c4(const u32 *rp, const u32 *ci, const u32 *rev,
+                                          const u64 *key, u32 n, unsigned char *scratch,
+                                          u64 stride, u32 *work, u64 *C4v, u64 *C4e) {
+    __shared__ u32 sh_src, sh_nt, sh_next;
+    __shared__ u64 sh_red[WAVES_PER_WG];
+    unsigned char *base = scratch + (u64)blockIdx.x * stride;
+    u32 *cnt = (u32 *)base;
+    u32 *touched = (u32 *)align256((unsigned char *)(cnt + n));
+    for (;;) {
+        u32 x = next_source(work, &sh_src);
+        if (x >= n) break;
+        const u64 kx = key[x];
+        const u32 bx = rp[x], dx = rp[x + 1] - bx;
+        if (threadIdx.x == 0) { sh_nt = 0; sh_next = 0; }
+        __syncthreads();
+        wave_loop(&sh_next, dx, [&](u32 i) {
+            u32 y = ci[bx + i];
+            if (key[y] >= kx) return;
+            for (u32 s = rp[y] + lane_id(); s < rp[y + 1]; s += WAVE) {
+                u32 z = ci[s];
+                if (z != x && key[z] < kx) {
+                    u32 old = atomicAdd(&cnt[z], 1u);
+                    if (old == 0) touched[atomicAdd(&sh_nt, 1u)] = z;
+                }
+            }
+        });
+        __syncthreads();
+        const u32 nt = sh_nt;
+        u64 loc = 0;
+        for (u32 t = threadIdx.x; t < nt; t += WG) {
+            u32 z = touched[t];
+            u64 v = c2(cnt[z]);
+            loc += v;
+            atomic_add_u64(&C4v[z], v);
+        }
+        u64 tot = block_sum_u64(loc, sh_red);
+        if (threadIdx.x == 0) { atomic_add_u64(&C4v[x], tot); sh_next = 0; }
+        __syncthreads();
+        wave_loop(&sh_next, dx, [&](u32 i) {
+            u32 sxy = bx + i;
+            u32 y = ci[sxy];
+            if (key[y] >= kx) return;
+            u64 acc = 0;
+            for (u32 s = rp[y] + lane_id(); s < rp[y + 1]; s += WAVE) {
+                u32 z = ci[s];
+                if (z != x && key[z] < kx) {
+                    u32 c = cnt[z];
+                    if (c > 1) {
+                        acc += c - 1;
+                        atomicAdd(&C4e[s], (u64)(c - 1));
+                        atomicAdd(&C4e[rev[s]], (u64)(c - 1));
+                    }
+                }
+            }
+            acc = wave_sum_u64(acc);
+            if (lane_id() == 0 && acc) {
+                atomicAdd(&C4v[y], acc);
+                atomicAdd(&C4e[sxy], acc);
+                atomicAdd(&C4e[rev[sxy]], acc);
+            }
+        });
+        __syncthreads();
+        for (u32 t = threadIdx.x; t < nt; t += WG) cnt[touched[t]] = 0;
+    }
+}
+
+// ---- 4- and 5-cliques.  For a source a, G+(a) is the graph induced on its
+// out-neighbours; its adjacency is held as bit rows (und: undirected, outm:
+// oriented).  Every clique is counted once from its lowest-ranked vertex a:
+// triangle records (a,b,c) give the 4-clique apexes inside N+(a) as
+// und[b] & und[c] (and oriented ones as outm[b] & outm[c]); 5-cliques are
+// oriented 4-clique apexes of those.
+//   pass 1: K4(u) (orbit 14), K4(e) (edge orbit E11), K4(t) per triangle
+//           (apexes inside N+(a) plus one credit from each 4-clique whose
+//           lowest vertex precedes the triangle), 5-cliques (orbit 72).
+//   pass 2: orbit 70, sum over 4-cliques containing u of K4(opposite
+//           triangle) - 1 (Theorem 5vertexorbit), needing the final K4(t).
+#define CLQ_LDS_D 384
+#define CLQ_LDS_W (CLQ_LDS_D / 64)
+
+__device__ inline u64 tri_find(u64 arc, u32 z, const u64 *tri_ptr, const u32 *tri_c,
+                               DevState *st) {
+    u64 b = tri_ptr[arc];
+    u32 len = (u32)(tri_ptr[arc + 1] - b);
+    u32 i = bfind(tri_c + b, len, z);
+    if (i == UNSET) { atomicOr(&st->err, ERRB_INTERNAL); return b; }
+    return b + i;
+}
+__device__ inline u64 arc_find(u32 x, u32 y, const u64 *out_ptr, const u32 *out_nbr,
+                               DevState *st) {
+    u64 b = out_ptr[x];
+    u32 len = (u32)(out_ptr[x + 1] - b);
+    u32 i = bfind(out_nbr + b, len, y);
+    if (i == UNSET) { atomicOr(&st->err, ERRB_INTERNAL); return b; }
+    return b + i;
+}
+
+__global__ void __launch_bounds__(WG) k_clique(int pass, u32 n, const u32 *rev,
+                                              const u64 *out_ptr, const u32 *out_nbr,
+                                              const u32 *out_slot, const u64 *tri_ptr,
+                                              const u32 *tri_c, const u32 *tri_sbc,
+                                              unsigned char *scratch, u64 stride, u32 dcap,
+                                              u32 *work, u32 *K4t, u64 *K4v, u64 *K4e,
+                                              u64 *ni, DevState *st) {
+    __shared__ u32 sh_src, sh_next;
+    __shared__ u64 sh_red[WAVES_PER_WG];
+    __shared__ u32 l_nbr[CLQ_LDS_D];
+    __shared__ u64 l_und[CLQ_LDS_D * CLQ_LDS_W];
+    __shared__ u64 l_out[CLQ_LDS_D * CLQ_LDS_W];
+    __shared__ u64 l_acc[CLQ_LDS_D];
+    __shared__ u64 l_acc5[CLQ_LDS_D];
+    unsigned char *gbase = scratch + (u64)blockIdx.x * stride;
+    for (;;) {
+        u32 a = next_source(work, &sh_src);
+        if (a >= n) break;
+        const u64 pa = out_ptr[a];
+        const u32 D = (u32)(out_ptr[a + 1] - pa);
+        if (D < 2) continue;
+        const u32 W = (D + 63) / 64;
+        u32 *nbr;
+        u64 *und, *outm, *acc, *acc5;
+        if (D <= CLQ_LDS_D) {
+            nbr = l_nbr; und = l_und; outm = l_out; acc = l_acc; acc5 = l_acc5;
+        } else {
+            if (D > dcap) {  // cannot happen: out-degrees are bounded by the peel level
+                if (threadIdx.x == 0) atomicOr(&st->err, ERRB_INTERNAL);
+                continue;
+            }
+            nbr = (u32 *)gbase;
+            und = (u64 *)align256((unsigned char *)(nbr + D));
+            outm = und + (u64)D * W;
+            acc = outm + (u64)D * W;
+            acc5 = acc + D;
+        }
+        for (u32 i = threadIdx.x; i < D; i += WG) {
+            nbr[i] = out_nbr[pa + i];
+            acc[i] = 0;
+            acc5[i] = 0;
+        }
+        for (u32 i = threadIdx.x; i < D * W; i += WG) { und[i] = 0; outm[i] = 0; }
+        if (threadIdx.x == 0) sh_next = 0;
+        __syncthreads();
+        wave_loop(&sh_next, D, [&](u32 i) {
+            u32 b = nbr[i];
+            for (u64 q = out_ptr[b] + lane_id(); q < out_ptr[b + 1]; q += WAVE) {
+                u32 j = bfind(nbr, D, out_nbr[q]);
+                if (j != UNSET) {
+                    atomicOr(&outm[(u64)i * W + j / 64], 1ull << (j % 64));
+                    atomicOr(&und[(u64)i * W + j / 64], 1ull << (j % 64));
+                    atomicOr(&und[(u64)j * W + i / 64], 1ull << (i % 64));
+                }
+            }
+        });
+        __syncthreads();
+        const u64 r0 = tri_ptr[pa], r1 = tri_ptr[pa + D];
+        u64 tot = 0, tot5 = 0;
+        for (u64 r = r0 + threadIdx.x; r < r1; r += WG) {
+            // owner arc of record r: largest p in [pa, pa+D) with tri_ptr[p] <= r
+            u32 lo = 0, hi = D;
+            while (hi - lo > 1) {
+                u32 mid = (lo + hi) >> 1;
+                if (tri_ptr[pa + mid] <= r) lo = mid; else hi = mid;
+            }
+            const u32 i = lo;
+            const u32 c = tri_c[r];
+            const u32 j = bfind(nbr, D, c);
+            if (j == UNSET) { atomicOr(&st->err, ERRB_INTERNAL); continue; }
+            const u64 *ri = und + (u64)i * W, *rj = und + (u64)j * W;
+            const u64 *oi = outm + (u64)i * W, *oj = outm + (u64)j * W;
+            if (pass == 1) {
+                u32 k = 0;
+                for (u32 w = 0; w < W; w++) k += __popcll(ri[w] & rj[w]);
+                if (k) {
+                    atomicAdd(&K4t[r], k);
+                    u32 sbc = tri_sbc[r];
+                    atomicAdd(&K4e[sbc], (u64)k);
+                    atomicAdd(&K4e[rev[sbc]], (u64)k);
+                    atomicAdd(&acc[i], (u64)k);
+                    atomicAdd(&acc[j], (u64)k);
+                    tot += k;
+                }
+                const u32 b = nbr[i];
+                for (u32 w = 0; w < W; w++) {
+                    u64 msk = oi[w] & oj[w];
+                    while (msk) {
+                        u32 l = w * 64 + __ffsll((long long)msk) - 1;
+                        msk &= msk - 1;
+                        u32 d = nbr[l];
+                        // the triangle (b,c,d) gets this 4-clique as an apex a
+                        u64 arc = arc_find(b, c, out_ptr, out_nbr, st);
+                        atomicAdd(&K4t[tri_find(arc, d, tri_ptr, tri_c, st)], 1u);
+                        const u64 *ol = outm + (u64)l * W;
+                        u32 c5 = 0;
+                        for (u32 w2 = 0; w2 < W; w2++) c5 += __popcll(oi[w2] & oj[w2] & ol[w2]);
+                        if (c5) {
+                            tot5 += c5;
+                            atomicAdd(&acc5[i], (u64)c5);
+                            atomicAdd(&acc5[j], (u64)c5);
+                            atomicAdd(&acc5[l], (u64)c5);
+                            for (u32 w2 = 0; w2 < W; w2++) {
+                                u64 m5 = oi[w2] & oj[w2] & ol[w2];
+                                while (m5) {
+                                    u32 e = w2 * 64 + __ffsll((long long)m5) - 1;
+                                    m5 &= m5 - 1;
+                                    atomicAdd(&acc5[e], 1ull);
+                                }
+                            }
+                        }
+                    }
+                }
+            } else {
+                const u32 b = nbr[i];
+                const u64 kt_abc = (u64)K4t[r];
+                for (u32 w = 0; w < W; w++) {
+                    u64 msk = oi[w] & oj[w];
+                    while (msk) {
+                        u32 l = w * 64 + __ffsll((long long)msk) - 1;
+                        msk &= msk - 1;
+                        u32 d = nbr[l];
+                        u64 arc_bc = arc_find(b, c, out_ptr, out_nbr, st);
+                        tot += (u64)K4t[tri_find(arc_bc, d, tri_ptr, tri_c, st)] - 1;
+                        atomicAdd(&acc[i], (u64)K4t[tri_find(pa + j, d, tri_ptr, tri_c, st)] - 1);
+                        atomicAdd(&acc[j], (u64)K4t[tri_find(pa + i, d, tri_ptr, tri_c, st)] - 1);
+                        atomicAdd(&acc[l], kt_abc - 1);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        u64 t4 = block_sum_u64(tot, sh_red);
+        u64 t5 = pass == 1 ? block_sum_u64(tot5, sh_red) : 0;
+        for (u32 i = threadIdx.x; i < D; i += WG) {
+            u32 v = nbr[i];
+            if (pass == 1) {
+                u64 h = acc[i] / 2;
+                if (h) {
+                    u32 s = out_slot[pa + i];
+                    atomicAdd(&K4e[s], h);
+                    atomicAdd(&K4e[rev[s]], h);
+                    atomicAdd(&K4v[v], h);
+                }
+                atomic_add_u64(&NI(v, 72), acc5[i]);
+            } else {
+                atomic_add_u64(&NI(v, 70), acc[i]);
+            }
+        }
+        if (threadIdx.x == 0) {
+            if (pass == 1) {
+                atomic_add_u64(&K4v[a], t4 / 3);
+                atomic_add_u64(&NI(a, 72), t5);
+            } else {
+                atomic_add_u64(&NI(a, 70), t4);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Orbits 66 and 71 from K4(t): each vertex u of triangle t = {u,v,x} gets
+// C(K4(t),2) (orbit 71) and K4(t) (T(v,x) - 2) (orbit 66: the sum over the
+// 4-cliques at u of T over the opposite triangle's edges, minus 6, regrouped
+// by the triangle that the 4-clique shares with u).
+__global__ void k_tri_k4terms(const u32 *src, const u32 *ci, const u32 *T, u64 ntri,
+                              const u32 *tri_c, const u32 *tri_sab, const u32 *tri_sac,
+                              const u32 *tri_sbc, const u32 *K4t, u64 *ni) {
+    for (u64 r = GTID; r < ntri; r += GSTRIDE) {
+        u64 kt = K4t[r];
+        if (!kt) continue;
+        u32 sab = tri_sab[r];
+        u32 a = src[sab], b = ci[sab], c = tri_c[r];
+        u64 q = c2((i64)kt);
+        atomic_add_u64(&NI(a, 71), q);
+        atomic_add_u64(&NI(b, 71), q);
+        atomic_add_u64(&NI(c, 71), q);
+        atomic_add_u64(&NI(a, 66), kt * ((u64)T[tri_sbc[r]] - 2));
+        atomic_add_u64(&NI(b, 66), kt * ((u64)T[tri_sac[r]] - 2));
+        atomic_add_u64(&NI(c, 66), kt * ((u64)T[sab] - 2));
+    }
+}
+
+// ---- pair sweep over wedges and diamonds (the undirected 2-hop sweep).
+// For a source a and every b > a with s = |N(a) & N(b)| >= 2 (pairs with
+// s <= 1 contribute to none of these orbits), with S = N(a) & N(b):
+//   ta = sum_{y in S} T(a,y),  tb = sum_{y in S} T(y,b),  e = |E(S)|
+// (edges inside S, i.e. the diamonds with tips a, b: D(a,b)).  Then
+//   pair terms to a (and symmetrically to b), Theorem 5vertexorbit:
+//     36: C(s,2)(d(b)-2)    50: C(s,3)    51: (tb - [a~b] s)(s-1)
+//     63: e (s-2)
+//   centre terms to y in S:  49: C(s-1,2)   62: e
+//   chord terms (each diamond with tips a,b and chord (y,z)) to y and z:
+//     64: s - 2
+//   wheel terms: for y in N(a), K(a,y,b) = |N(a) & N(y) & N(b)| and
+//     68: C(K,2) to a and to b;  Q(a,y) = sum_b C(K,2) (orbit 69 of y is half
+//     the sum of Q over the arcs into y).
+// The remaining subtractions (36: -N13, 51: -2 N12, 62: -N13) happen in the
+// per-vertex combine.
+struct PairScratch {
+    u32 *S;
+    u64 *E, *TA, *TB;
+    unsigned char *mark;
+    u32 *touched;
+    u32 *K;   // WAVES_PER_WG x n
+    u32 *tk;  // WAVES_PER_WG x n
+};
+__device__ inline PairScratch pair_scratch(unsigned char *base, u32 n) {
+    PairScratch p;
+    p.S = (u32 *)base;
+    p.E = (u64 *)align256((unsigned char *)(p.S + n));
+    p.TA = (u64 *)align256((unsigned char *)(p.E + n));
+    p.TB = (u64 *)align256((unsigned char *)(p.TA + n));
+    p.mark = align256((unsigned char *)(p.TB + n));
+    p.touched = (u32 *)align256(p.mark + n);
+    p.K = (u32 *)align256((unsigned char *)(p.touched + n));
+    p.tk = (u32 *)align256((unsigned char *)(p.K + (u64)WAVES_PER_WG * n));
+    return p;
+}
+
+__global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, const u32 *src,
+                                             const u32 *rev, const u32 *deg, const u32 *T,
+                                             const u64 *tl_ptr, const uint2 *tl, u32 n,
+                                             unsigned char *scratch, u64 stride, u32 *work,
+                                             u64 *Q, u64 *ni) {
+    __shared__ u32 sh_src, sh_nt, sh_next;
+    __shared__ u32 sh_ntk[WAVES_PER_WG];
+    __shared__ u64 sh_red[WAVES_PER_WG];
+    PairScratch P = pair_scratch(scratch + (u64)blockIdx.x * stride, n);
+    u32 *Kw = P.K + (u64)wave_in_wg() * n;
+    u32 *tkw = P.tk + (u64)wave_in_wg() * n;
+    for (;;) {
+        const u32 a = next_source(work, &sh_src);
+        if (a >= n) break;
+        const u32 ba = rp[a], da = rp[a + 1] - ba;
+        if (da < 2) continue;
+        const u64 dega = da;
+        for (u32 i = threadIdx.x; i < da; i += WG) P.mark[ci[ba + i]] = 1;
+        if (threadIdx.x == 0) { sh_nt = 0; sh_next = 0; }
+        __syncthreads();
+        // wedges a - y - b, b > a
+        wave_loop(&sh_next, da, [&](u32 iy) {
+            const u32 say = ba + iy, y = ci[say];
+            const u64 tay = T[say];
+            const u32 by = rp[y], ey = rp[y + 1];
+            const u32 st0 = by + lbound(ci + by, ey - by, a + 1);
+            for (u32 s = st0 + lane_id(); s < ey; s += WAVE) {
+                const u32 b = ci[s];
+                u32 old = atomicAdd(&P.S[b], 1u);
+                if (old == 0) P.touched[atomicAdd(&sh_nt, 1u)] = b;
+                atomicAdd(&P.TA[b], tay);
+                atomicAdd(&P.TB[b], (u64)T[s]);
+            }
+        });
+        __syncthreads();
+        if (threadIdx.x == 0) sh_next = 0;
+        __syncthreads();
+        // diamonds with tip a, chord (y,z), y < z, other tip b > a
+        wave_loop(&sh_next, da, [&](u32 iy) {
+            const u32 say = ba + iy, y = ci[say];
+            if (T[say] == 0) return;
+            TLView tv = tl_view(say, src, ci, rev, T, tl_ptr, tl);
+            u64 accy = 0;
+            for (u32 k = 0; k < tv.len; k++) {
+                uint2 ez = tv.get(k);  // (slot(a,z), slot(y,z))
+                const u32 z = ci[ez.x];
+                if (z <= y) continue;
+                TLView tw = tl_view(ez.y, src, ci, rev, T, tl_ptr, tl);
+                u64 chord = 0;
+                for (u32 q = lane_id(); q < tw.len; q += WAVE) {
+                    uint2 eb = tw.get(q);  // (slot(y,b), slot(z,b))
+                    const u32 b = ci[eb.x];
+                    if (b <= a) continue;
+                    atomicAdd(&P.E[b], 1ull);
+                    chord += (u64)P.S[b] - 2;
+                }
+                chord = wave_sum_u64(chord);
+                if (lane_id() == 0) atomic_add_u64(&NI(z, 64), chord);
+                accy += chord;
+            }
+            if (lane_id() == 0) atomic_add_u64(&NI(y, 64), accy);
+        });
+        __syncthreads();
+        // pair terms
+        const u32 nt = sh_nt;
+        u64 l36 = 0, l50 = 0, l51 = 0, l63 = 0;
+        for (u32 t = threadIdx.x; t < nt; t += WG) {
+            const u32 b = P.touched[t];
+            const u64 s = P.S[b];
+            if (s < 2) continue;
+            const u64 adj = P.mark[b];
+            const u64 e = P.E[b];
+            const u64 cs2 = c2((i64)s), cs3 = c3((i64)s);
+            l36 += cs2 * ((u64)deg[b] - 2);
+            l50 += cs3;
+            l51 += (P.TB[b] - adj * s) * (s - 1);
+            l63 += e * (s - 2);
+            atomic_add_u64(&NI(b, 36), cs2 * (dega - 2));
+            atomic_add_u64(&NI(b, 50), cs3);
+            atomic_add_u64(&NI(b, 51), (P.TA[b] - adj * s) * (s - 1));
+            atomic_add_u64(&NI(b, 63), e * (s - 2));
+        }
+        l36 = block_sum_u64(l36, sh_red);
+        l50 = block_sum_u64(l50, sh_red);
+        l51 = block_sum_u64(l51, sh_red);
+        l63 = block_sum_u64(l63, sh_red);
+        if (threadIdx.x == 0) {
+            atomic_add_u64(&NI(a, 36), l36);
+            atomic_add_u64(&NI(a, 50), l50);
+            atomic_add_u64(&NI(a, 51), l51);
+            atomic_add_u64(&NI(a, 63), l63);
+            sh_next = 0;
+        }
+        __syncthreads();
+        // centre terms, then the wheel maps of (a, y) with a per-wave map
+        if (lane_id() == 0) sh_ntk[wave_in_wg()] = 0;
+        u64 l68 = 0;
+        wave_loop(&sh_next, da, [&](u32 iy) {
+            const u32 say = ba + iy, y = ci[say];
+            const u32 by = rp[y], ey = rp[y + 1];
+            const u32 st0 = by + lbound(ci + by, ey - by, a + 1);
+            u64 a49 = 0, a62 = 0;
+            for (u32 s = st0 + lane_id(); s < ey; s += WAVE) {
+                const u32 b = ci[s];
+                const u32 sb = P.S[b];
+                if (sb >= 2) {
+                    a49 += c2((i64)sb - 1);
+                    a62 += P.E[b];
+                }
+            }
+            a49 = wave_sum_u64(a49);
+            a62 = wave_sum_u64(a62);
+            if (lane_id() == 0) {
+                atomic_add_u64(&NI(y, 49), a49);
+                atomic_add_u64(&NI(y, 62), a62);
+            }
+            if (T[say] < 2) return;
+            TLView tv = tl_view(say, src, ci, rev, T, tl_ptr, tl);
+            u32 *ntk = &sh_ntk[wave_in_wg()];
+            for (u32 k = 0; k < tv.len; k++) {
+                uint2 ez = tv.get(k);
+                TLView tw = tl_view(ez.y, src, ci, rev, T, tl_ptr, tl);
+                for (u32 q = lane_id(); q < tw.len; q += WAVE) {
+                    const u32 b = ci[tw.get(q).x];
+                    if (b <= a) continue;
+                    u32 old = atomicAdd(&Kw[b], 1u);
+                    if (old == 0) tkw[atomicAdd(ntk, 1u)] = b;
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            const u32 m = *ntk;
+            u64 q = 0;
+            for (u32 t = lane_id(); t < m; t += WAVE) {
+                const u32 b = tkw[t];
+                const u64 v = c2((i64)atomicExch(&Kw[b], 0u));
+                q += v;
+                atomic_add_u64(&NI(b, 68), v);
+            }
+            q = wave_sum_u64(q);
+            if (lane_id() == 0) {
+                Q[say] = q;
+                *ntk = 0;
+            }
+            l68 += q;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        });
+        __syncthreads();
+        // l68 is uniform within each wave (computed from wave sums)
+        if (lane_id() == 0) atomic_add_u64(&NI(a, 68), l68);
+        for (u32 t = threadIdx.x; t < nt; t += WG) {
+            const u32 b = P.touched[t];
+            P.S[b] = 0; P.E[b] = 0; P.TA[b] = 0; P.TB[b] = 0;
+        }
+        for (u32 i = threadIdx.x; i < da; i += WG) P.mark[ci[ba + i]] = 0;
+        __syncthreads();
+    }
+}
+
+// ---- 5-cycles (orbit 34): the procedure of the 5-cycle theorem.  Every
+// 5-cycle has exactly one directed 3-path i <- j <- k -> l whose closing
+// wedge i - w - l is not in-in (not both i->w and l->w).  For a source l:
+//   W(i) = non-in-in wedges between l and i,  P(i) = directed 3-paths
+//   from i to l.  Each 3-path credits i, j, k, l with
+//   W(i) - [i~k] - [j~l] (removing w = k and w = j), and each non-in-in
+//   wedge l - w - i credits w with P(i) minus the tailed triangles
+//   (Fig. TaileTri): [w->i] Tin(w,l) + [w->l][w->i] (Tmid(w->i) - [l->i]).
+struct C5Scratch {
+    u32 *Wm;
+    u64 *P, *CI;
+    u32 *touched;
+    unsigned char *mark;
+};
+__device__ inline C5Scratch c5_scratch(unsigned char *base, u32 n) {
+    C5Scratch c;
+    c.Wm = (u32 *)base;
+    c.P = (u64 *)align256((unsigned char *)(c.Wm + n));
+    c.CI = (u64 *)align256((unsigned char *)(c.P + n));
+    c.touched = (u32 *)align256((unsigned char *)(c.CI + n));
+    c.mark = align256((unsigned char *)(c.touched + n));
+    return c;
+}
+
+__device__ inline bool out_adjacent(u32 k, u32 i, const u64 *out_ptr, const u32 *out_nbr) {
+    u64 b = out_ptr[k];
+    return bfind(out_nbr + b, (u32)(out_ptr[k + 1] - b), i) != UNSET;
+}
+
+__global__ void __launch_bounds__(WG) k_c5(const u32 *rp, const u32 *ci, const u64 *key,
+                                          const u64 *out_ptr, const u32 *out_nbr,
+                                          const u32 *out_slot, const u32 *Tin, const u32 *Tmid,
+                                          u32 n, unsigned char *scratch, u64 stride, u32 *work,
+                                          u64 *ni) {
+    __shared__ u32 sh_src, sh_nt, sh_next;
+    __shared__ u64 sh_red[WAVES_PER_WG];
+    C5Scratch C = c5_scratch(scratch + (u64)blockIdx.x * stride, n);
+    for (;;) {
+        const u32 l = next_source(work, &sh_src);
+        if (l >= n) break;
+        const u32 bl = rp[l], dl = rp[l + 1] - bl;
+        if (dl < 2) continue;
+        const u64 kl = key[l];
+        for (u32 i = threadIdx.x; i < dl; i += WG) C.mark[ci[bl + i]] = 1;
+        if (threadIdx.x == 0) { sh_nt = 0; sh_next = 0; }
+        __syncthreads();
+        // non-in-in wedges l - w - i, and 3-paths i <- j <- k -> l
+        wave_loop(&sh_next, dl, [&](u32 iw) {
+            const u32 w = ci[bl + iw];
+            if (key[w] > kl) {  // l -> w, then w -> i
+                for (u64 q = out_ptr[w] + lane_id(); q < out_ptr[w + 1]; q += WAVE)
+                    atomicAdd(&C.Wm[out_nbr[q]], 1u);
+            } else {  // w -> l, then any i ~ w
+                for (u32 s = rp[w] + lane_id(); s < rp[w + 1]; s += WAVE) {
+                    const u32 i = ci[s];
+                    if (i != l) atomicAdd(&C.Wm[i], 1u);
+                }
+                // w plays k: 3-paths i <- j <- w -> l
+                const u32 k = w;
+                for (u64 qj = out_ptr[k]; qj < out_ptr[k + 1]; qj++) {
+                    const u32 j = out_nbr[qj];
+                    if (j == l) continue;
+                    const u64 jl = C.mark[j];
+                    for (u64 qi = out_ptr[j] + lane_id(); qi < out_ptr[j + 1]; qi += WAVE) {
+                        const u32 i = out_nbr[qi];
+                        if (i == l) continue;
+                        u64 old = atomicAdd(&C.P[i], 1ull);
+                        if (old == 0) C.touched[atomicAdd(&sh_nt, 1u)] = i;
+                        const u64 ik = out_adjacent(k, i, out_ptr, out_nbr) ? 1 : 0;
+                        atomic_add_u64(&C.CI[i], ik + jl);
+                    }
+                }
+            }
+        });
+        __syncthreads();
+        if (threadIdx.x == 0) sh_next = 0;
+        __syncthreads();
+        // credits of j and k per 3-path, and of w per wedge
+        wave_loop(&sh_next, dl, [&](u32 iw) {
+            const u32 slw = bl + iw;
+            const u32 w = ci[slw];
+            const u64 kw = key[w];
+            u64 accw = 0;
+            if (kw > kl) {  // l -> w -> i
+                const u64 tin = Tin[slw];
+                for (u64 q = out_ptr[w] + lane_id(); q < out_ptr[w + 1]; q += WAVE) {
+                    const u32 i = out_nbr[q];
+                    const u64 p = C.P[i];
+                    if (p) accw += p - tin;  // w -> i holds; w -> l does not
+                }
+            } else {  // w -> l
+                const u64 tin = Tin[slw];
+                for (u32 s = rp[w] + lane_id(); s < rp[w + 1]; s += WAVE) {
+                    const u32 i = ci[s];
+                    if (i == l) continue;
+                    const u64 p = C.P[i];
+                    if (!p) continue;
+                    u64 corr = 0;
+                    if (key[i] > kw) {  // w -> i
+                        const bool li = C.mark[i] && key[i] > kl;  // l -> i
+                        corr = tin + (u64)Tmid[s] - (li ? 1 : 0);
+                    }
+                    accw += p - corr;
+                }
+                // 3-paths through k = w: credits of j and k
+                const u32 k = w;
+                u64 acck = 0;
+                for (u64 qj = out_ptr[k]; qj < out_ptr[k + 1]; qj++) {
+                    const u32 j = out_nbr[qj];
+                    if (j == l) continue;
+                    const u64 jl = C.mark[j];
+                    u64 accj = 0;
+                    for (u64 qi = out_ptr[j] + lane_id(); qi < out_ptr[j + 1]; qi += WAVE) {
+                        const u32 i = out_nbr[qi];
+                        if (i == l) continue;
+                        const u64 ik = out_adjacent(k, i, out_ptr, out_nbr) ? 1 : 0;
+                        accj += (u64)C.Wm[i] - ik - jl;
+                    }
+                    accj = wave_sum_u64(accj);
+                    if (lane_id() == 0) atomic_add_u64(&NI(j, 34), accj);
+                    acck += accj;
+                }
+                if (lane_id() == 0) atomic_add_u64(&NI(k, 34), acck);
+            }
+            accw = wave_sum_u64(accw);
+            if (lane_id() == 0) atomic_add_u64(&NI(w, 34), accw);
+        });
+        __syncthreads();
+        // credits of i (summed over its 3-paths) and of l
+        const u32 nt = sh_nt;
+        u64 accl = 0;
+        for (u32 t = threadIdx.x; t < nt; t += WG) {
+            const u32 i = C.touched[t];
+            const u64 v = C.P[i] * (u64)C.Wm[i] - C.CI[i];
+            accl += v;
+            atomic_add_u64(&NI(i, 34), v);
+        }
+        accl = block_sum_u64(accl, sh_red);
+        if (threadIdx.x == 0) atomic_add_u64(&NI(l, 34), accl);
+        __syncthreads();
+        // reset: Wm was touched on every wedge endpoint, P/CI on 3-path ends
+        for (u32 t = threadIdx.x; t < nt; t += WG) {
+            const u32 i = C.touched[t];
+            C.P[i] = 0; C.CI[i] = 0;
+        }
+        if (threadIdx.x == 0) sh_next = 0;
+        __syncthreads();
+        wave_loop(&sh_next, dl, [&](u32 iw) {
+            const u32 w = ci[bl + iw];
+            if (key[w] > kl) {
+                for (u64 q = out_ptr[w] + lane_id(); q < out_ptr[w + 1]; q += WAVE) C.Wm[out_nbr[q]] = 0;
+            } else {
+                for (u32 s = rp[w] + lane_id(); s < rp[w + 1]; s += WAVE) C.Wm[ci[s]] = 0;
+            }
+        });
+        for (u32 i = threadIdx.x; i < dl; i += WG) C.mark[ci[bl + i]] = 0;
+        __syncthreads();
+    }
+}

@@ -1,0 +1,176 @@
+"""Thin Python binding of liborbit_hip.so (argument marshalling only).
+
+Every step of the counting runs in the library's HIP kernels; PyTorch only
+provides device memory and the current HIP stream.  Importing this module
+loads the library and fails loudly if it has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from .build import LIB
+
+NORB = 73
+ORB_NONINDUCED = 0x1
+ORB_TIMING = 0x2
+
+EXPORTS = ("orbit_num_orbits", "orbit_count", "orbit_workspace_query", "orbit_count_ex",
+           "orbit_strerror", "orbit_last_phase_times")
+
+
+class OrbError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        super().__init__(f"{where}: {status} ({_lib.orbit_strerror(status).decode()})")
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("flags", ctypes.c_uint32), ("num_wg", ctypes.c_uint32)]
+
+
+def _load():
+    if not os.path.exists(LIB):
+        raise ImportError(f"{LIB} is not built; run paper_1911_10616_amd.build.build()")
+    lib = ctypes.CDLL(LIB)
+    vp = ctypes.c_void_p
+    u64 = ctypes.c_uint64
+    lib.orbit_num_orbits.argtypes = [ctypes.c_int]
+    lib.orbit_num_orbits.restype = ctypes.c_int
+    lib.orbit_count.argtypes = [vp, vp, ctypes.c_uint32, u64, ctypes.c_int, vp]
+    lib.orbit_count.restype = ctypes.c_int
+    lib.orbit_workspace_query.argtypes = [vp, vp, ctypes.c_uint32, u64, ctypes.c_int, vp,
+                                          ctypes.POINTER(_Opts), ctypes.POINTER(u64)]
+    lib.orbit_workspace_query.restype = ctypes.c_int
+    lib.orbit_count_ex.argtypes = [vp, vp, ctypes.c_uint32, u64, ctypes.c_int, vp, vp, u64,
+                                   ctypes.POINTER(u64), vp, ctypes.POINTER(_Opts)]
+    lib.orbit_count_ex.restype = ctypes.c_int
+    lib.orbit_strerror.argtypes = [ctypes.c_int]
+    lib.orbit_strerror.restype = ctypes.c_char_p
+    lib.orbit_last_phase_times.argtypes = [ctypes.POINTER(ctypes.c_float),
+                                           ctypes.POINTER(ctypes.c_char_p), ctypes.c_int]
+    lib.orbit_last_phase_times.restype = ctypes.c_int
+    return lib
+
+
+_lib = _load()
+
+
+def num_orbits(k_max: int) -> int:
+    return _lib.orbit_num_orbits(k_max)
+
+
+def _dev_csr(row_ptr, col_idx, device="cuda"):
+    import torch
+    rp = torch.as_tensor(np.asarray(row_ptr, dtype=np.uint32).view(np.int32)) \
+        if not isinstance(row_ptr, torch.Tensor) else row_ptr
+    ci = torch.as_tensor(np.asarray(col_idx, dtype=np.uint32).view(np.int32)) \
+        if not isinstance(col_idx, torch.Tensor) else col_idx
+    rp = rp.to(device).contiguous()
+    ci = ci.to(device).contiguous()
+    if ci.numel() == 0:
+        ci = torch.zeros(1, dtype=torch.int32, device=device)
+    return rp, ci
+
+
+def _stream_ptr(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _opts(noninduced=False, timing=False, num_wg=0):
+    f = (ORB_NONINDUCED if noninduced else 0) | (ORB_TIMING if timing else 0)
+    return _Opts(f, num_wg)
+
+
+def workspace_bytes(row_ptr, col_idx, k_max=5, noninduced=False, num_wg=0, stream=None) -> int:
+    rp, ci = _dev_csr(row_ptr, col_idx)
+    n = rp.numel() - 1
+    m = int(rp[-1].item()) // 2 if n >= 0 else 0
+    out = ctypes.c_uint64(0)
+    o = _opts(noninduced, False, num_wg)
+    st = _lib.orbit_workspace_query(ctypes.c_void_p(rp.data_ptr()), ctypes.c_void_p(ci.data_ptr()),
+                                    n, m, k_max, _stream_ptr(stream), ctypes.byref(o),
+                                    ctypes.byref(out))
+    if st:
+        raise OrbError(st, "orbit_workspace_query")
+    return int(out.value)
+
+
+class Counter:
+    """Counts orbits of one graph repeatedly with a workspace allocated once.
+
+    row_ptr/col_idx: symmetric CSR (uint32 values; numpy arrays or int32
+    torch tensors holding the same bits).  Results are uint64 counts
+    returned as an int64 torch tensor of shape [n, K] holding the same bits
+    (use ``.cpu().numpy().view(np.uint64)``)."""
+
+    def __init__(self, row_ptr, col_idx, k_max=5, noninduced=False, num_wg=0, stream=None):
+        import torch
+        self.rp, self.ci = _dev_csr(row_ptr, col_idx)
+        self.n = self.rp.numel() - 1
+        self.m = int(self.rp[-1].item()) // 2
+        self.k_max = k_max
+        self.K = num_orbits(k_max)
+        if not self.K:
+            raise OrbError(-1, "k_max")
+        self.opts = _opts(noninduced, False, num_wg)
+        self.topts = _opts(noninduced, True, num_wg)
+        self.stream = stream
+        self.ws_bytes = workspace_bytes(self.rp, self.ci, k_max, noninduced, num_wg, stream)
+        self.ws = torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8, device=self.rp.device)
+        self.out = torch.empty((max(self.n, 1), self.K), dtype=torch.int64, device=self.rp.device)
+
+    def run(self, timing=False):
+        need = ctypes.c_uint64(0)
+        o = self.topts if timing else self.opts
+        st = _lib.orbit_count_ex(ctypes.c_void_p(self.rp.data_ptr()),
+                                 ctypes.c_void_p(self.ci.data_ptr()), self.n, self.m, self.k_max,
+                                 ctypes.c_void_p(self.out.data_ptr()),
+                                 ctypes.c_void_p(self.ws.data_ptr()), self.ws_bytes,
+                                 ctypes.byref(need), _stream_ptr(self.stream), ctypes.byref(o))
+        if st:
+            raise OrbError(st, "orbit_count_ex")
+        return self.out[: self.n]
+
+
+def count(row_ptr, col_idx, k_max=5, noninduced=False, num_wg=0) -> np.ndarray:
+    """uint64[n, K] orbit counts (induced unless noninduced=True)."""
+    c = Counter(row_ptr, col_idx, k_max, noninduced, num_wg)
+    return c.run().cpu().numpy().view(np.uint64)
+
+
+def count_minimal(row_ptr, col_idx, k_max=5) -> np.ndarray:
+    """The minimal C entry point orbit_count (internal workspace, null stream)."""
+    import torch
+    rp, ci = _dev_csr(row_ptr, col_idx)
+    n = rp.numel() - 1
+    m = int(rp[-1].item()) // 2
+    K = num_orbits(k_max)
+    out = torch.empty((max(n, 1), K), dtype=torch.int64, device=rp.device)
+    torch.cuda.synchronize()
+    st = _lib.orbit_count(ctypes.c_void_p(rp.data_ptr()), ctypes.c_void_p(ci.data_ptr()), n, m,
+                          k_max, ctypes.c_void_p(out.data_ptr()))
+    if st:
+        raise OrbError(st, "orbit_count")
+    return out[:n].cpu().numpy().view(np.uint64)
+
+
+def last_phase_times():
+    ms = (ctypes.c_float * 24)()
+    names = (ctypes.c_char_p * 24)()
+    k = _lib.orbit_last_phase_times(ms, names, 24)
+    return [(names[i].decode(), float(ms[i])) for i in range(k)]
+
+
+def raw_count_ex(rp, ci, n, m, k_max, counts, ws, ws_bytes, flags=0, stream=None):
+    """Direct call of orbit_count_ex with explicit arguments (tests)."""
+    need = ctypes.c_uint64(0)
+    o = _Opts(flags, 0)
+    st = _lib.orbit_count_ex(ctypes.c_void_p(rp), ctypes.c_void_p(ci), n, m, k_max,
+                             ctypes.c_void_p(counts), ctypes.c_void_p(ws), ws_bytes,
+                             ctypes.byref(need), _stream_ptr(stream), ctypes.byref(o))
+    return st, int(need.value)
