@@ -107,6 +107,14 @@ const char *orbit_strerror(int status);
  * strings) and returns the number of phases. */
 int orbit_last_phase_times(float *ms, const char **names, int max_phases);
 
+/* Work statistics of the calling thread's last orbit_count_ex with
+ * ORB_TIMING, for throughput and roofline reporting: vals[0..5] = n, m,
+ * triangles, degeneracy (largest peel level), wedges = sum over vertices of
+ * C(d,2), diamonds = sum over edges of C(T(e),2) (the pattern counts W(G)
+ * and D(G) in the running-time theorem of the paper's main-theorem
+ * section).  Writes up to max_vals values and returns how many. */
+int orbit_last_stats(uint64_t *vals, int max_vals);
+
 #ifdef __cplusplus
 }
 #endif

@@ -265,3 +265,19 @@ __global__ void k_transform(u64 *ni, u32 n, int K, int induced, u64 *out) {
             for (int i = 0; i < K; i++) out[u * K + i] = R[i];
     }
 }
+
+// Work statistics (reported with per-phase timing): wedges = sum of C(d,2)
+// over vertices, diamonds = sum of C(T(e),2) over edges.
+__global__ void k_stats(const u32 *src, const u32 *ci, const u32 *deg, const u32 *T, u32 n,
+                        u64 M2, DevState *st) {
+    u64 w = 0, d = 0;
+    for (u64 u = GTID; u < n; u += GSTRIDE) w += c2((i64)deg[u]);
+    for (u64 s = GTID; s < M2; s += GSTRIDE)
+        if (src[s] < ci[s]) d += c2((i64)T[s]);
+    w = wave_sum_u64(w);
+    d = wave_sum_u64(d);
+    if (lane_id() == 0) {
+        atomic_add_u64(&st->wedges, w);
+        atomic_add_u64(&st->diamonds, d);
+    }
+}

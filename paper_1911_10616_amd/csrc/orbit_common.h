@@ -36,6 +36,8 @@ struct DevState {
     u32 work[16];   // dynamic work counters of the per-source kernels
     u64 ntri;       // number of triangles
     u64 scan_total; // total of the last exclusive scan
+    u64 wedges;     // sum over vertices of C(d,2)
+    u64 diamonds;   // sum over edges of C(T(e),2)
 };
 
 // ---------------------------------------------------------------- binomials

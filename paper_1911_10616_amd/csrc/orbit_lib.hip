@@ -18,6 +18,7 @@ const int kMaxPhases = 24;
 thread_local float g_phase_ms[kMaxPhases];
 thread_local const char *g_phase_name[kMaxPhases];
 thread_local int g_nphase = 0;
+thread_local u64 g_stats[6];
 
 struct Buf {
     u64 off = 0, bytes = 0;
@@ -392,6 +393,7 @@ int count_impl(const u32 *rp, const u32 *ci, u32 n, u64 m, int k_max, u64 *count
     if (k_max >= 4) {
         rc = zero_scratch(0, n, scratch, L, s);
         if (rc) return rc;
+        tm.mark("zero_c4");
         k_c4<<<L.nwg, WG, 0, s>>>(rp, ci, rev, key, n, scratch, L.stride, work + wi++, C4v, C4e);
         HCHK(hipGetLastError());
         tm.mark("c4");
@@ -418,15 +420,17 @@ int count_impl(const u32 *rp, const u32 *ci, u32 n, u64 m, int k_max, u64 *count
                                                             tri_sac, tri_sbc, K4t, ni);
             HCHK(hipGetLastError());
         }
-        tm.mark("k4_terms");
+        tm.mark("clique2_k4terms");
         rc = zero_scratch(1, n, scratch, L, s);
         if (rc) return rc;
+        tm.mark("zero_pairs");
         k_pairs<<<L.nwg, WG, 0, s>>>(rp, ci, src, rev, deg, T, tlptr, tl, n, scratch, L.stride,
                                      work + wi++, Q, ni);
         HCHK(hipGetLastError());
         tm.mark("pairs");
         rc = zero_scratch(2, n, scratch, L, s);
         if (rc) return rc;
+        tm.mark("zero_c5");
         k_c5<<<L.nwg, WG, 0, s>>>(rp, ci, key, outptr, outnbr, outslot, Tin, Tmid, n, scratch,
                                   L.stride, work + wi++, ni);
         HCHK(hipGetLastError());
@@ -438,9 +442,17 @@ int count_impl(const u32 *rp, const u32 *ci, u32 n, u64 m, int k_max, u64 *count
     k_transform<<<grid_for(n, WG), WG, 0, s>>>(ni, n, K, (flags & ORB_NONINDUCED) ? 0 : 1, counts);
     HCHK(hipGetLastError());
     tm.mark("combine");
+    if (flags & ORB_TIMING) {
+        k_stats<<<grid_for(M2 > n ? M2 : n, WG), WG, 0, s>>>(src, ci, deg, T, n, M2, st);
+        HCHK(hipGetLastError());
+    }
     rc = read_state(st, &hs, s);
     if (rc) return rc;
     tm.finish();
+    if (flags & ORB_TIMING) {
+        g_stats[0] = n; g_stats[1] = m; g_stats[2] = ntri; g_stats[3] = hs.maxlevel;
+        g_stats[4] = hs.wedges; g_stats[5] = hs.diamonds;
+    }
     if (hs.err) return err_to_status(hs.err);
     return ORB_OK;
 }
@@ -510,6 +522,12 @@ const char *orbit_strerror(int status) {
         case ORB_E_INTERNAL: return "internal consistency check failed";
         default: return "unknown status";
     }
+}
+
+int orbit_last_stats(uint64_t *vals, int max_vals) {
+    int k = max_vals < 6 ? max_vals : 6;
+    for (int i = 0; i < k; i++) vals[i] = g_stats[i];
+    return k;
 }
 
 int orbit_last_phase_times(float *ms, const char **names, int max_phases) {

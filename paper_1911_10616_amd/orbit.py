@@ -18,7 +18,7 @@ ORB_NONINDUCED = 0x1
 ORB_TIMING = 0x2
 
 EXPORTS = ("orbit_num_orbits", "orbit_count", "orbit_workspace_query", "orbit_count_ex",
-           "orbit_strerror", "orbit_last_phase_times")
+           "orbit_strerror", "orbit_last_phase_times", "orbit_last_stats")
 
 
 class OrbError(RuntimeError):
@@ -52,6 +52,8 @@ def _load():
     lib.orbit_last_phase_times.argtypes = [ctypes.POINTER(ctypes.c_float),
                                            ctypes.POINTER(ctypes.c_char_p), ctypes.c_int]
     lib.orbit_last_phase_times.restype = ctypes.c_int
+    lib.orbit_last_stats.argtypes = [ctypes.POINTER(u64), ctypes.c_int]
+    lib.orbit_last_stats.restype = ctypes.c_int
     return lib
 
 
@@ -164,6 +166,14 @@ def last_phase_times():
     names = (ctypes.c_char_p * 24)()
     k = _lib.orbit_last_phase_times(ms, names, 24)
     return [(names[i].decode(), float(ms[i])) for i in range(k)]
+
+
+def last_stats():
+    """Work statistics of the last timed call (dict)."""
+    v = (ctypes.c_uint64 * 6)()
+    k = _lib.orbit_last_stats(v, 6)
+    keys = ("n", "m", "triangles", "degeneracy", "wedges", "diamonds")
+    return {keys[i]: int(v[i]) for i in range(k)}
 
 
 def raw_count_ex(rp, ci, n, m, k_max, counts, ws, ws_bytes, flags=0, stream=None):
