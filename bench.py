@@ -70,6 +70,21 @@ def cpu_baseline(rp, ci, seconds: float, seed: int = 1):
     }
 
 
+def measured_traffic(workload):
+    """HBM bytes per k_pairs launch from the committed rocprofv3 counter
+    record, if it was taken on this workload and on the current kernel
+    source; None otherwise."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"k_pairs_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+        return None
+    return rec["fetch_bytes"] + rec["write_bytes"]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -133,7 +148,8 @@ def main():
     achieved = alg_bytes / (dom_ms / 1000.0) / 1e9
     roofline = {"kernel": "k_pairs", "bound": "hbm", "achieved": round(achieved, 3),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6),
-                "traffic": None, "alg_bytes": alg_bytes, "avg_ms": round(dom_ms, 3)}
+                "traffic": measured_traffic(args.workload), "alg_bytes": alg_bytes,
+                "avg_ms": round(dom_ms, 3)}
 
     line = {
         "metric": "edges/s for all <=5-vertex orbit counts (bit-exact), HBM GB/s vs peak",
