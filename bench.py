@@ -31,8 +31,26 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 WORKLOADS = {
     "chunglu1m": "Chung-Lu n=1M, mean 20, gamma 2.1, w<=50k, 1e7 pairs, seed 0x5EED0002",
     "er2000": "Erdos-Renyi G(n=2000, p=0.005), seed 0x5EED0001",
+    "chunglu1m_perm": "Chung-Lu n=1M as above, vertex ids permuted at random (seed 0x5EED0006)",
     "rmat22": "R-MAT scale 22, edge factor 16, (0.57,0.19,0.19,0.05), seed 0x5EED0003",
 }
+TRAIN_WORKLOAD = "chunglu250k"
+
+
+def train_cost_model(orbit, seed=1, iters=1500, batch=4096):
+    """Cost-model weights trained on the per-source step counts of a smaller
+    graph of the same family (Chung-Lu n=250k, mean 20, gamma 2.1), so the
+    timed graph is never seen in training."""
+    import torch
+    from paper_1911_10616_amd import graphgen as gg
+    rp, ci = gg.workload(TRAIN_WORKLOAD)
+    n = len(rp) - 1
+    feat = torch.empty((n, 3), dtype=torch.float32, device="cuda")
+    steps = torch.empty(n, dtype=torch.int64, device="cuda")
+    orbit.Counter(rp, ci, 5, features_out=feat, steps_out=steps).run()
+    w = orbit.mlp_init(seed=seed)
+    loss = orbit.mlp_train(w, feat, steps, iters=iters, batch=batch, lr=3e-3, seed=seed)
+    return w, loss
 
 
 def cpu_baseline(rp, ci, seconds: float, seed: int = 1):
@@ -91,6 +109,8 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="chunglu1m", choices=sorted(WORKLOADS))
+    ap.add_argument("--schedule", default="id", choices=("id", "static", "mlp"),
+                    help="order of sources in the per-source kernels")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -120,7 +140,10 @@ def main():
     rp, ci = gg.workload(args.workload)
     n = len(rp) - 1
     m = ci.size // 2
-    counter = orbit.Counter(rp, ci, k_max=5)
+    w, train_loss = (None, None)
+    if args.schedule == "mlp":
+        w, train_loss = train_cost_model(orbit)
+    counter = orbit.Counter(rp, ci, k_max=5, schedule=args.schedule, mlp_weights=w)
     stream = torch.cuda.current_stream()
 
     for _ in range(args.warmup):
@@ -165,11 +188,14 @@ def main():
         "dtype": "u64",
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload], "n": n, "m": m, "k_max": 5,
-                   "orbits": 73, "output": "induced uint64 counts n x 73"},
+                   "orbits": 73, "output": "induced uint64 counts n x 73",
+                   "schedule": args.schedule},
         "roofline": roofline,
         "phases_ms": {k: round(v, 3) for k, v in phases.items()},
         "work": stats,
     }
+    if train_loss is not None:
+        line["cost_model"] = {"trained_on": TRAIN_WORKLOAD, "mse_log2_steps": round(train_loss, 4)}
     if not args.no_cpu_baseline and rank == 0:
         line["cpu_baseline"] = cpu_baseline(rp, ci, args.cpu_seconds)
     if rank == 0:

@@ -69,9 +69,29 @@ extern "C" {
 #define ORB_NONINDUCED 0x1u /* return non-induced counts DM(u, theta) */
 #define ORB_TIMING 0x2u     /* record per-phase times (orbit_last_phase_times) */
 
+/* order in which the per-source kernels take their sources (the counts
+ * are the same under every schedule; only the work balance changes) */
+#define ORB_SCHED_ID 0u     /* ascending vertex id */
+#define ORB_SCHED_STATIC 1u /* heaviest first by degree thresholds:
+                               bins of 4*(log2(1+d) + log2(1+d+)) */
+#define ORB_SCHED_MLP 2u    /* heaviest first by the cost model's prediction
+                               (bins of 4 * predicted log2 steps) */
+
+/* cost model: a 3 -> 32 -> 32 -> 1 fp32 ReLU network, parameters packed as
+ * W1[32][3], b1[32], W2[32][32], b2[32], W3[32], b3 */
+#define ORB_MLP_PARAMS 1217
+
 typedef struct orb_opts {
-    uint32_t flags;     /* ORB_* option bits */
-    uint32_t num_wg;    /* persistent workgroups for the per-source kernels; 0 = default */
+    uint32_t flags;           /* ORB_* option bits */
+    uint32_t num_wg;          /* persistent workgroups for the per-source kernels; 0 = default */
+    uint32_t schedule;        /* ORB_SCHED_* */
+    uint32_t reserved;        /* must be 0 */
+    const float *mlp_weights; /* device, ORB_MLP_PARAMS floats; needed by ORB_SCHED_MLP */
+    float *features_out;      /* device, n*3 floats, nullable: per-vertex cost features
+                                 (log2(1+d+(u)), log2(1+sum_{w in N+(u)} d+(w)), log2(1+d(u)))
+                                 under the degeneracy orientation */
+    uint64_t *steps_out;      /* device, n uint64, nullable: per-source loop iterations
+                                 of the pair sweep (the cost model's training target) */
 } orb_opts;
 
 /* Number of output columns K for k_max (3, 4 or 5); 0 if k_max is invalid. */
@@ -106,6 +126,32 @@ const char *orbit_strerror(int status);
  * ORB_TIMING: writes up to max_phases values and their names (static
  * strings) and returns the number of phases. */
 int orbit_last_phase_times(float *ms, const char **names, int max_phases);
+
+/* ---- cost model (learned scheduler).  All pointers are device pointers;
+ * the calls are asynchronous on `stream` and return after enqueueing. */
+
+/* Initialise the ORB_MLP_PARAMS weights from `seed` (He-uniform weights,
+ * zero biases). */
+int orbit_mlp_init(float *weights, uint32_t seed, void *stream);
+
+/* Predictions out[i] (log2 step count) for count feature rows (3 floats). */
+int orbit_mlp_predict(const float *weights, const float *features, uint32_t count, float *out,
+                      void *stream);
+
+/* Full-batch gradient of the mean squared error between the predictions and
+ * targets (floats), or log2(1 + steps) when targets is NULL: grad receives
+ * ORB_MLP_PARAMS floats, loss one float.  Both are overwritten. */
+int orbit_mlp_grad(const float *weights, const float *features, const float *targets,
+                   const uint64_t *steps, uint32_t count, float *grad, float *loss,
+                   void *stream);
+
+/* Train the weights in place with Adam for `iters` mini-batch steps of
+ * `batch` samples drawn (by a counter-based hash of seed and step) from the
+ * count rows, target log2(1 + steps).  state: 3*ORB_MLP_PARAMS + 1 floats
+ * of scratch (moments, gradient, last mini-batch loss in the final float). */
+int orbit_mlp_train(const float *features, const uint64_t *steps, uint32_t count,
+                    float *weights, float *state, uint32_t iters, uint32_t batch, float lr,
+                    uint32_t seed, void *stream);
 
 /* Work statistics of the calling thread's last orbit_count_ex with
  * ORB_TIMING, for throughput and roofline reporting: vals[0..5] = n, m,

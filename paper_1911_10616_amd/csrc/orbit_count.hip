@@ -139,9 +139,14 @@ __global__ void k_edge_e7e9(const u32 *src, const u32 *ci, const u32 *rev, const
 // One workgroup per source vertex at a time (dynamic), with dense per-WG
 // scratch arrays indexed by vertex id that are restored to zero after
 // every source.
-__device__ inline u32 next_source(u32 *counter, u32 *sh) {
+// The sources come from a queue: the i-th fetch gets order[i] (a schedule),
+// or i itself when there is no schedule; n once the queue is empty.
+__device__ inline u32 next_source(u32 *counter, u32 *sh, const u32 *order, u32 n) {
     __syncthreads();
-    if (threadIdx.x == 0) *sh = atomicAdd(counter, 1u);
+    if (threadIdx.x == 0) {
+        u32 i = atomicAdd(counter, 1u);
+        *sh = i < n ? (order ? order[i] : i) : n;
+    }
     __syncthreads();
     return *sh;
 }
@@ -180,14 +185,15 @@ __device__ inline unsigned char *align256(unsigned char *p) {
 // Gives C4(u) (orbit 8) and C4(e) (edge orbit E5).
 __global__ void __launch_bounds__(WG) k_c4(const u32 *rp, const u32 *ci, const u32 *rev,
                                           const u64 *key, u32 n, unsigned char *scratch,
-                                          u64 stride, u32 *work, u64 *C4v, u64 *C4e) {
+                                          u64 stride, u32 *work, const u32 *order, u64 *C4v,
+                                          u64 *C4e) {
     __shared__ u32 sh_src, sh_nt, sh_next;
     __shared__ u64 sh_red[WAVES_PER_WG];
     unsigned char *base = scratch + (u64)blockIdx.x * stride;
     u32 *cnt = (u32 *)base;
     u32 *touched = (u32 *)align256((unsigned char *)(cnt + n));
     for (;;) {
-        u32 x = next_source(work, &sh_src);
+        u32 x = next_source(work, &sh_src, order, n);
         if (x >= n) break;
         const u64 kx = key[x];
         const u32 bx = rp[x], dx = rp[x + 1] - bx;
@@ -280,8 +286,8 @@ __global__ void __launch_bounds__(WG) k_clique(int pass, u32 n, const u32 *rev,
                                               const u32 *out_slot, const u64 *tri_ptr,
                                               const u32 *tri_c, const u32 *tri_sbc,
                                               unsigned char *scratch, u64 stride, u32 dcap,
-                                              u32 *work, u32 *K4t, u64 *K4v, u64 *K4e,
-                                              u64 *ni, DevState *st) {
+                                              u32 *work, const u32 *order, u32 *K4t, u64 *K4v,
+                                              u64 *K4e, u64 *ni, DevState *st) {
     __shared__ u32 sh_src, sh_next;
     __shared__ u64 sh_red[WAVES_PER_WG];
     __shared__ u32 l_nbr[CLQ_LDS_D];
@@ -291,7 +297,7 @@ __global__ void __launch_bounds__(WG) k_clique(int pass, u32 n, const u32 *rev,
     __shared__ u64 l_acc5[CLQ_LDS_D];
     unsigned char *gbase = scratch + (u64)blockIdx.x * stride;
     for (;;) {
-        u32 a = next_source(work, &sh_src);
+        u32 a = next_source(work, &sh_src, order, n);
         if (a >= n) break;
         const u64 pa = out_ptr[a];
         const u32 D = (u32)(out_ptr[a + 1] - pa);
@@ -499,7 +505,7 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
                                              const u32 *rev, const u32 *deg, const u32 *T,
                                              const u64 *tl_ptr, const uint2 *tl, u32 n,
                                              unsigned char *scratch, u64 stride, u32 *work,
-                                             u64 *Q, u64 *ni) {
+                                             const u32 *order, u64 *steps, u64 *Q, u64 *ni) {
     __shared__ u32 sh_src, sh_nt, sh_next;
     __shared__ u32 sh_ntk[WAVES_PER_WG];
     __shared__ u64 sh_red[WAVES_PER_WG];
@@ -507,11 +513,12 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
     u32 *Kw = P.K + (u64)wave_in_wg() * n;
     u32 *tkw = P.tk + (u64)wave_in_wg() * n;
     for (;;) {
-        const u32 a = next_source(work, &sh_src);
+        const u32 a = next_source(work, &sh_src, order, n);
         if (a >= n) break;
         const u32 ba = rp[a], da = rp[a + 1] - ba;
         if (da < 2) continue;
         const u64 dega = da;
+        u64 nsteps = 0;  // loop iterations of this thread for this source
         for (u32 i = threadIdx.x; i < da; i += WG) P.mark[ci[ba + i]] = 1;
         if (threadIdx.x == 0) { sh_nt = 0; sh_next = 0; }
         __syncthreads();
@@ -523,6 +530,7 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
             const u32 st0 = by + lbound(ci + by, ey - by, a + 1);
             for (u32 s = st0 + lane_id(); s < ey; s += WAVE) {
                 const u32 b = ci[s];
+                nsteps++;
                 u32 old = atomicAdd(&P.S[b], 1u);
                 if (old == 0) P.touched[atomicAdd(&sh_nt, 1u)] = b;
                 atomicAdd(&P.TA[b], tay);
@@ -547,6 +555,7 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
                 for (u32 q = lane_id(); q < tw.len; q += WAVE) {
                     uint2 eb = tw.get(q);  // (slot(y,b), slot(z,b))
                     const u32 b = ci[eb.x];
+                    nsteps++;
                     if (b <= a) continue;
                     atomicAdd(&P.E[b], 1ull);
                     chord += (u64)P.S[b] - 2;
@@ -600,6 +609,7 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
             for (u32 s = st0 + lane_id(); s < ey; s += WAVE) {
                 const u32 b = ci[s];
                 const u32 sb = P.S[b];
+                nsteps++;
                 if (sb >= 2) {
                     a49 += c2((i64)sb - 1);
                     a62 += P.E[b];
@@ -619,6 +629,7 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
                 TLView tw = tl_view(ez.y, src, ci, rev, T, tl_ptr, tl);
                 for (u32 q = lane_id(); q < tw.len; q += WAVE) {
                     const u32 b = ci[tw.get(q).x];
+                    nsteps++;
                     if (b <= a) continue;
                     u32 old = atomicAdd(&Kw[b], 1u);
                     if (old == 0) tkw[atomicAdd(ntk, 1u)] = b;
@@ -653,6 +664,10 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
             P.S[b] = 0; P.E[b] = 0; P.TA[b] = 0; P.TB[b] = 0;
         }
         for (u32 i = threadIdx.x; i < da; i += WG) P.mark[ci[ba + i]] = 0;
+        if (steps) {  // per-source work, the training target of the scheduler
+            u64 tot = block_sum_u64(nsteps, sh_red);
+            if (threadIdx.x == 0) steps[a] += tot;
+        }
         __syncthreads();
     }
 }
@@ -690,16 +705,17 @@ __global__ void __launch_bounds__(WG) k_c5(const u32 *rp, const u32 *ci, const u
                                           const u64 *out_ptr, const u32 *out_nbr,
                                           const u32 *out_slot, const u32 *Tin, const u32 *Tmid,
                                           u32 n, unsigned char *scratch, u64 stride, u32 *work,
-                                          u64 *ni) {
+                                          const u32 *order, u64 *steps, u64 *ni) {
     __shared__ u32 sh_src, sh_nt, sh_next;
     __shared__ u64 sh_red[WAVES_PER_WG];
     C5Scratch C = c5_scratch(scratch + (u64)blockIdx.x * stride, n);
     for (;;) {
-        const u32 l = next_source(work, &sh_src);
+        const u32 l = next_source(work, &sh_src, order, n);
         if (l >= n) break;
         const u32 bl = rp[l], dl = rp[l + 1] - bl;
         if (dl < 2) continue;
         const u64 kl = key[l];
+        u64 nsteps = 0;  // loop iterations of this thread for this source
         for (u32 i = threadIdx.x; i < dl; i += WG) C.mark[ci[bl + i]] = 1;
         if (threadIdx.x == 0) { sh_nt = 0; sh_next = 0; }
         __syncthreads();
@@ -707,12 +723,15 @@ __global__ void __launch_bounds__(WG) k_c5(const u32 *rp, const u32 *ci, const u
         wave_loop(&sh_next, dl, [&](u32 iw) {
             const u32 w = ci[bl + iw];
             if (key[w] > kl) {  // l -> w, then w -> i
-                for (u64 q = out_ptr[w] + lane_id(); q < out_ptr[w + 1]; q += WAVE)
+                for (u64 q = out_ptr[w] + lane_id(); q < out_ptr[w + 1]; q += WAVE) {
                     atomicAdd(&C.Wm[out_nbr[q]], 1u);
+                    nsteps++;
+                }
             } else {  // w -> l, then any i ~ w
                 for (u32 s = rp[w] + lane_id(); s < rp[w + 1]; s += WAVE) {
                     const u32 i = ci[s];
                     if (i != l) atomicAdd(&C.Wm[i], 1u);
+                    nsteps++;
                 }
                 // w plays k: 3-paths i <- j <- w -> l
                 const u32 k = w;
@@ -722,6 +741,7 @@ __global__ void __launch_bounds__(WG) k_c5(const u32 *rp, const u32 *ci, const u
                     const u64 jl = C.mark[j];
                     for (u64 qi = out_ptr[j] + lane_id(); qi < out_ptr[j + 1]; qi += WAVE) {
                         const u32 i = out_nbr[qi];
+                        nsteps++;
                         if (i == l) continue;
                         u64 old = atomicAdd(&C.P[i], 1ull);
                         if (old == 0) C.touched[atomicAdd(&sh_nt, 1u)] = i;
@@ -796,6 +816,10 @@ __global__ void __launch_bounds__(WG) k_c5(const u32 *rp, const u32 *ci, const u
         }
         accl = block_sum_u64(accl, sh_red);
         if (threadIdx.x == 0) atomic_add_u64(&NI(l, 34), accl);
+        if (steps) {
+            const u64 tot = block_sum_u64(nsteps, sh_red);
+            if (threadIdx.x == 0) steps[l] += tot;
+        }
         __syncthreads();
         // reset: Wm was touched on every wedge endpoint, P/CI on 3-path ends
         for (u32 t = threadIdx.x; t < nt; t += WG) {

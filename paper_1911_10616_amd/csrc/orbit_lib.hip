@@ -10,6 +10,7 @@
 #include "orbit_prep.hip"
 #include "orbit_count.hip"
 #include "orbit_combine.hip"
+#include "orbit_sched.hip"
 #include "../../include/orbit_hip.h"
 
 namespace {
@@ -34,7 +35,7 @@ struct Layout {
     u64 p1_end = 0;
     // phase 2
     Buf tri_c, tri_sab, tri_sac, tri_sbc, T, Tin, Tmid, tllen, tlptr, tlcur, tl, E7, E9, C4e,
-        K4e, Q, K4t, Tv, N1, C4v, K4v, ni, scratch;
+        K4e, Q, K4t, Tv, N1, C4v, K4v, ni, feat, pred, sbin, shist, order, scratch;
     u64 total = 0;
     u64 stride = 0;
     u32 nwg = 0;
@@ -109,6 +110,11 @@ void layout_phase2(Layout &L, u32 n, u64 m, u64 ntri, u32 dmax, int k_max, bool 
     place(c, L.C4v, 8ull * n + 8);
     place(c, L.K4v, 8ull * n + 8);
     place(c, L.ni, ni_in_out ? 0 : 8ull * ORB_NORB * n + 8);
+    place(c, L.feat, 12ull * n + 12);
+    place(c, L.pred, 4ull * n + 4);
+    place(c, L.sbin, 4ull * n + 4);
+    place(c, L.shist, 4ull * SCHED_BINS);
+    place(c, L.order, 4ull * n + 4);
     u64 stride = 8ull * n + 512;  // 4-cycle maps
     if (k_max >= 5) {
         u64 ps = pair_stride(n);
@@ -118,8 +124,8 @@ void layout_phase2(Layout &L, u32 n, u64 m, u64 ntri, u32 dmax, int k_max, bool 
     if (cs > stride) stride = cs;
     stride = align_up(stride, 256);
     u32 nwg = nwg_req ? nwg_req : 512;
-    // keep the per-source scratch within 16 GiB unless asked otherwise
-    const u64 cap = 16ull << 30;
+    // keep the per-source scratch within 48 GiB unless asked otherwise
+    const u64 cap = 48ull << 30;
     while (!nwg_req && nwg > 64 && (u64)nwg * stride > cap) nwg /= 2;
     L.nwg = nwg;
     L.stride = stride;
@@ -174,11 +180,12 @@ int zero_ranges(int which, u32 n, ZeroRange *r) {
     return 2;
 }
 
-int zero_scratch(int which, u32 n, unsigned char *scratch, const Layout &L, hipStream_t s) {
+int zero_scratch(int which, u32 n, unsigned char *scratch, const Layout &L, u32 nwg,
+                 hipStream_t s) {
     ZeroRange r[2];
     int k = zero_ranges(which, n, r);
     for (int i = 0; i < k; i++)
-        HCHK(hipMemset2DAsync(scratch + r[i].off, L.stride, 0, r[i].len, L.nwg, s));
+        HCHK(hipMemset2DAsync(scratch + r[i].off, L.stride, 0, r[i].len, nwg, s));
     return ORB_OK;
 }
 
@@ -319,6 +326,9 @@ int count_impl(const u32 *rp, const u32 *ci, u32 n, u64 m, int k_max, u64 *count
     const int K = orbit_num_orbits(k_max);
     if (!K) return ORB_E_INVALID_ARG;
     if (flags & ~(ORB_NONINDUCED | ORB_TIMING)) return ORB_E_INVALID_ARG;
+    const u32 sched = opts ? opts->schedule : ORB_SCHED_ID;
+    if (sched > ORB_SCHED_MLP || (opts && opts->reserved)) return ORB_E_INVALID_ARG;
+    if (sched == ORB_SCHED_MLP && !opts->mlp_weights) return ORB_E_INVALID_ARG;
     if (2 * m >= (1ull << 32)) return ORB_E_INVALID_ARG;
     if (!rp || (m && !ci) || (!counts && !query_only && n)) return ORB_E_INVALID_ARG;
     Layout L;
@@ -368,6 +378,32 @@ int count_impl(const u32 *rp, const u32 *ci, u32 n, u64 m, int k_max, u64 *count
     HCHK(hipMemsetAsync(ni, 0, 8ull * ORB_NORB * n, s));
     tm.mark("zero");
 
+    // schedule of the per-source kernels
+    float *feat = (opts && opts->features_out) ? opts->features_out : at<float>(ws, L.feat);
+    const u32 *order = nullptr;
+    if ((opts && opts->features_out) || sched != ORB_SCHED_ID) {
+        k_features<<<grid_waves(n), WG, 0, s>>>(deg, outptr, outnbr, n, feat);
+        HCHK(hipGetLastError());
+    }
+    if (sched != ORB_SCHED_ID) {
+        float *pred = nullptr;
+        if (sched == ORB_SCHED_MLP) {
+            pred = at<float>(ws, L.pred);
+            k_mlp_predict<<<grid_for(n, WG), WG, 0, s>>>(opts->mlp_weights, feat, n, pred);
+        }
+        u32 *sbin = at<u32>(ws, L.sbin), *shist = at<u32>(ws, L.shist);
+        u32 *ord = at<u32>(ws, L.order);
+        HCHK(hipMemsetAsync(shist, 0, 4ull * SCHED_BINS, s));
+        k_sched_bins<<<grid_for(n, WG), WG, 0, s>>>(feat, pred, n, sbin, shist);
+        k_sched_offsets<<<1, 64, 0, s>>>(shist);
+        k_sched_scatter<<<grid_for(n, WG), WG, 0, s>>>(sbin, n, shist, ord);
+        HCHK(hipGetLastError());
+        order = ord;
+    }
+    u64 *steps_out = opts ? (u64 *)opts->steps_out : nullptr;
+    if (steps_out) HCHK(hipMemsetAsync(steps_out, 0, 8ull * n, s));
+    tm.mark("schedule");
+
     if (ntri) {
         k_tri_fill<<<grid_for(m, WG), WG, 0, s>>>(src, outptr, outnbr, outslot, m, triptr, tri_c,
                                                   tri_sab, tri_sac, tri_sbc);
@@ -391,15 +427,16 @@ int count_impl(const u32 *rp, const u32 *ci, u32 n, u64 m, int k_max, u64 *count
     u32 *work = st->work;
     int wi = 0;
     if (k_max >= 4) {
-        rc = zero_scratch(0, n, scratch, L, s);
+        rc = zero_scratch(0, n, scratch, L, L.nwg, s);
         if (rc) return rc;
         tm.mark("zero_c4");
-        k_c4<<<L.nwg, WG, 0, s>>>(rp, ci, rev, key, n, scratch, L.stride, work + wi++, C4v, C4e);
+        k_c4<<<L.nwg, WG, 0, s>>>(rp, ci, rev, key, n, scratch, L.stride, work + wi++, order,
+                                  C4v, C4e);
         HCHK(hipGetLastError());
         tm.mark("c4");
         if (ntri) {
             k_clique<<<L.nwg, WG, 0, s>>>(1, n, rev, outptr, outnbr, outslot, triptr, tri_c,
-                                          tri_sbc, scratch, L.stride, dmax, work + wi++, K4t, K4v, K4e,
+                                          tri_sbc, scratch, L.stride, dmax, work + wi++, order, K4t, K4v, K4e,
                                           ni, st);
             HCHK(hipGetLastError());
         }
@@ -414,25 +451,25 @@ int count_impl(const u32 *rp, const u32 *ci, u32 n, u64 m, int k_max, u64 *count
     if (k_max >= 5) {
         if (ntri) {
             k_clique<<<L.nwg, WG, 0, s>>>(2, n, rev, outptr, outnbr, outslot, triptr, tri_c,
-                                          tri_sbc, scratch, L.stride, dmax, work + wi++, K4t, K4v, K4e,
+                                          tri_sbc, scratch, L.stride, dmax, work + wi++, order, K4t, K4v, K4e,
                                           ni, st);
             k_tri_k4terms<<<grid_for(ntri, WG), WG, 0, s>>>(src, ci, T, ntri, tri_c, tri_sab,
                                                             tri_sac, tri_sbc, K4t, ni);
             HCHK(hipGetLastError());
         }
         tm.mark("clique2_k4terms");
-        rc = zero_scratch(1, n, scratch, L, s);
+        rc = zero_scratch(1, n, scratch, L, L.nwg, s);
         if (rc) return rc;
         tm.mark("zero_pairs");
         k_pairs<<<L.nwg, WG, 0, s>>>(rp, ci, src, rev, deg, T, tlptr, tl, n, scratch, L.stride,
-                                     work + wi++, Q, ni);
+                                     work + wi++, order, steps_out, Q, ni);
         HCHK(hipGetLastError());
         tm.mark("pairs");
-        rc = zero_scratch(2, n, scratch, L, s);
+        rc = zero_scratch(2, n, scratch, L, L.nwg < 256 ? L.nwg : 256, s);
         if (rc) return rc;
         tm.mark("zero_c5");
-        k_c5<<<L.nwg, WG, 0, s>>>(rp, ci, key, outptr, outnbr, outslot, Tin, Tmid, n, scratch,
-                                  L.stride, work + wi++, ni);
+        k_c5<<<L.nwg < 256 ? L.nwg : 256, WG, 0, s>>>(rp, ci, key, outptr, outnbr, outslot, Tin, Tmid, n, scratch,
+                                  L.stride, work + wi++, order, steps_out, ni);
         HCHK(hipGetLastError());
         tm.mark("c5");
     }
@@ -506,6 +543,52 @@ int orbit_count(const uint32_t *row_ptr, const uint32_t *col_idx, uint32_t n, ui
                         nullptr);
     (void)hipFree(ws);
     return rc;
+}
+
+int orbit_mlp_init(float *weights, uint32_t seed, void *stream) {
+    if (!weights) return ORB_E_INVALID_ARG;
+    k_mlp_init<<<(MLP_NPARAM + WG - 1) / WG, WG, 0, (hipStream_t)stream>>>(weights, seed);
+    return hipGetLastError() == hipSuccess ? ORB_OK : ORB_E_DEVICE;
+}
+
+int orbit_mlp_predict(const float *weights, const float *features, uint32_t count, float *out,
+                      void *stream) {
+    if (!weights || (count && (!features || !out))) return ORB_E_INVALID_ARG;
+    if (!count) return ORB_OK;
+    k_mlp_predict<<<grid_for(count, WG), WG, 0, (hipStream_t)stream>>>(weights, features, count,
+                                                                        out);
+    return hipGetLastError() == hipSuccess ? ORB_OK : ORB_E_DEVICE;
+}
+
+int orbit_mlp_grad(const float *weights, const float *features, const float *targets,
+                   const uint64_t *steps, uint32_t count, float *grad, float *loss,
+                   void *stream) {
+    if (!weights || !features || !grad || !loss || !count || (!targets && !steps))
+        return ORB_E_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    k_zero_f32<<<(MLP_NPARAM + WG - 1) / WG, WG, 0, s>>>(grad, MLP_NPARAM);
+    k_zero_f32<<<1, WG, 0, s>>>(loss, 1);
+    k_mlp_grad<<<grid_for((count + MLP_TILE - 1) / MLP_TILE, 1), WG, 0, s>>>(
+        weights, features, targets, (const u64 *)steps, count, count, 1, 0, 0, grad, loss);
+    return hipGetLastError() == hipSuccess ? ORB_OK : ORB_E_DEVICE;
+}
+
+int orbit_mlp_train(const float *features, const uint64_t *steps, uint32_t count,
+                    float *weights, float *state, uint32_t iters, uint32_t batch, float lr,
+                    uint32_t seed, void *stream) {
+    if (!features || !steps || !weights || !state || !count || !batch) return ORB_E_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    float *m = state, *v = state + MLP_NPARAM, *grad = state + 2 * MLP_NPARAM;
+    float *loss = state + 3 * MLP_NPARAM;
+    k_zero_f32<<<(2 * MLP_NPARAM + WG - 1) / WG, WG, 0, s>>>(state, 2 * MLP_NPARAM);
+    const unsigned gblocks = grid_for((batch + MLP_TILE - 1) / MLP_TILE, 1);
+    for (uint32_t t = 1; t <= iters; t++) {
+        k_zero_f32<<<(MLP_NPARAM + 1 + WG - 1) / WG, WG, 0, s>>>(grad, MLP_NPARAM + 1);
+        k_mlp_grad<<<gblocks, WG, 0, s>>>(weights, features, nullptr, (const u64 *)steps, count,
+                                          batch, 0, seed, t, grad, loss);
+        k_mlp_adam<<<(MLP_NPARAM + WG - 1) / WG, WG, 0, s>>>(weights, grad, m, v, t, lr);
+    }
+    return hipGetLastError() == hipSuccess ? ORB_OK : ORB_E_DEVICE;
 }
 
 const char *orbit_strerror(int status) {

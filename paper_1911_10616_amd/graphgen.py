@@ -19,7 +19,7 @@ import numpy as np
 __all__ = [
     "csr_from_edges", "erdos_renyi", "chung_lu", "rmat", "barabasi_albert",
     "complete", "cycle", "star", "complete_bipartite", "path", "from_edge_list",
-    "random_small", "CONFIG_SEED_BASE", "workload",
+    "random_small", "relabel", "CONFIG_SEED_BASE", "workload",
 ]
 
 CONFIG_SEED_BASE = 0x5EED0000
@@ -185,12 +185,26 @@ def random_small(n: int, p: float, seed: int):
     return erdos_renyi(n, p, seed)
 
 
+def relabel(row_ptr, col_idx, seed: int):
+    """The same graph with vertex ids permuted uniformly at random (vertex
+    u becomes perm[u]); real graphs carry ids unrelated to degree."""
+    n = len(row_ptr) - 1
+    perm = np.random.Generator(np.random.PCG64(seed)).permutation(n)
+    src = np.repeat(np.arange(n, dtype=np.int64), np.diff(row_ptr).astype(np.int64))
+    keep = src < col_idx
+    return csr_from_edges(n, perm[src[keep]], perm[col_idx[keep].astype(np.int64)])
+
+
 def workload(name: str):
     """The five named synthetic workloads (seed = 0x5EED0000 + index)."""
     if name == "er2000":
         return erdos_renyi(2000, 0.005, CONFIG_SEED_BASE + 1)
     if name == "chunglu1m":
         return chung_lu(1_000_000, 20.0, 2.1, 50_000.0, 10_000_000, CONFIG_SEED_BASE + 2)
+    if name == "chunglu1m_perm":
+        return relabel(*workload("chunglu1m"), CONFIG_SEED_BASE + 6)
+    if name == "chunglu250k":  # a smaller graph of the same family (cost-model training)
+        return chung_lu(250_000, 20.0, 2.1, 12_500.0, 2_500_000, CONFIG_SEED_BASE + 7)
     if name == "rmat22":
         return rmat(22, 16, seed=CONFIG_SEED_BASE + 3)
     if name == "rmat24":

@@ -16,9 +16,13 @@ from .build import LIB
 NORB = 73
 ORB_NONINDUCED = 0x1
 ORB_TIMING = 0x2
+SCHED_ID, SCHED_STATIC, SCHED_MLP = 0, 1, 2
+SCHEDULES = {"id": SCHED_ID, "static": SCHED_STATIC, "mlp": SCHED_MLP}
+MLP_PARAMS = 1217
 
 EXPORTS = ("orbit_num_orbits", "orbit_count", "orbit_workspace_query", "orbit_count_ex",
-           "orbit_strerror", "orbit_last_phase_times", "orbit_last_stats")
+           "orbit_strerror", "orbit_last_phase_times", "orbit_last_stats", "orbit_mlp_init",
+           "orbit_mlp_predict", "orbit_mlp_grad", "orbit_mlp_train")
 
 
 class OrbError(RuntimeError):
@@ -28,7 +32,10 @@ class OrbError(RuntimeError):
 
 
 class _Opts(ctypes.Structure):
-    _fields_ = [("flags", ctypes.c_uint32), ("num_wg", ctypes.c_uint32)]
+    _fields_ = [("flags", ctypes.c_uint32), ("num_wg", ctypes.c_uint32),
+                ("schedule", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("mlp_weights", ctypes.c_void_p), ("features_out", ctypes.c_void_p),
+                ("steps_out", ctypes.c_void_p)]
 
 
 def _load():
@@ -54,6 +61,15 @@ def _load():
     lib.orbit_last_phase_times.restype = ctypes.c_int
     lib.orbit_last_stats.argtypes = [ctypes.POINTER(u64), ctypes.c_int]
     lib.orbit_last_stats.restype = ctypes.c_int
+    lib.orbit_mlp_init.argtypes = [vp, ctypes.c_uint32, vp]
+    lib.orbit_mlp_init.restype = ctypes.c_int
+    lib.orbit_mlp_predict.argtypes = [vp, vp, ctypes.c_uint32, vp, vp]
+    lib.orbit_mlp_predict.restype = ctypes.c_int
+    lib.orbit_mlp_grad.argtypes = [vp, vp, vp, vp, ctypes.c_uint32, vp, vp, vp]
+    lib.orbit_mlp_grad.restype = ctypes.c_int
+    lib.orbit_mlp_train.argtypes = [vp, vp, ctypes.c_uint32, vp, vp, ctypes.c_uint32,
+                                    ctypes.c_uint32, ctypes.c_float, ctypes.c_uint32, vp]
+    lib.orbit_mlp_train.restype = ctypes.c_int
     return lib
 
 
@@ -83,9 +99,14 @@ def _stream_ptr(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-def _opts(noninduced=False, timing=False, num_wg=0):
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def _opts(noninduced=False, timing=False, num_wg=0, schedule=SCHED_ID, mlp_weights=None,
+          features_out=None, steps_out=None):
     f = (ORB_NONINDUCED if noninduced else 0) | (ORB_TIMING if timing else 0)
-    return _Opts(f, num_wg)
+    return _Opts(f, num_wg, schedule, 0, _ptr(mlp_weights), _ptr(features_out), _ptr(steps_out))
 
 
 def workspace_bytes(row_ptr, col_idx, k_max=5, noninduced=False, num_wg=0, stream=None) -> int:
@@ -110,7 +131,13 @@ class Counter:
     returned as an int64 torch tensor of shape [n, K] holding the same bits
     (use ``.cpu().numpy().view(np.uint64)``)."""
 
-    def __init__(self, row_ptr, col_idx, k_max=5, noninduced=False, num_wg=0, stream=None):
+    def __init__(self, row_ptr, col_idx, k_max=5, noninduced=False, num_wg=0, stream=None,
+                 schedule="id", mlp_weights=None, features_out=None, steps_out=None):
+        """schedule: "id", "static" or "mlp" (source order of the per-source
+        kernels; needs mlp_weights, a float32 device tensor of MLP_PARAMS
+        values, for "mlp").  features_out (float32 [n, 3]) and steps_out
+        (int64 [n], uint64 bits) receive the cost features and per-source
+        pair-sweep step counts on every run when given."""
         import torch
         self.rp, self.ci = _dev_csr(row_ptr, col_idx)
         self.n = self.rp.numel() - 1
@@ -119,8 +146,12 @@ class Counter:
         self.K = num_orbits(k_max)
         if not self.K:
             raise OrbError(-1, "k_max")
-        self.opts = _opts(noninduced, False, num_wg)
-        self.topts = _opts(noninduced, True, num_wg)
+        sched = SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule)
+        extra = dict(schedule=sched, mlp_weights=mlp_weights, features_out=features_out,
+                     steps_out=steps_out)
+        self._keep = (mlp_weights, features_out, steps_out)
+        self.opts = _opts(noninduced, False, num_wg, **extra)
+        self.topts = _opts(noninduced, True, num_wg, **extra)
         self.stream = stream
         self.ws_bytes = workspace_bytes(self.rp, self.ci, k_max, noninduced, num_wg, stream)
         self.ws = torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8, device=self.rp.device)
@@ -176,10 +207,54 @@ def last_stats():
     return {keys[i]: int(v[i]) for i in range(k)}
 
 
+def _check(st, where):
+    if st:
+        raise OrbError(st, where)
+
+
+def mlp_init(seed=1, stream=None):
+    """Fresh cost-model weights (float32 device tensor of MLP_PARAMS)."""
+    import torch
+    w = torch.empty(MLP_PARAMS, dtype=torch.float32, device="cuda")
+    _check(_lib.orbit_mlp_init(w.data_ptr(), seed, _stream_ptr(stream)), "orbit_mlp_init")
+    return w
+
+
+def mlp_predict(weights, features, stream=None):
+    import torch
+    n = features.shape[0]
+    out = torch.empty(max(n, 1), dtype=torch.float32, device=features.device)
+    _check(_lib.orbit_mlp_predict(weights.data_ptr(), features.data_ptr(), n, out.data_ptr(),
+                                  _stream_ptr(stream)), "orbit_mlp_predict")
+    return out[:n]
+
+
+def mlp_grad(weights, features, targets=None, steps=None, stream=None):
+    """(grad [MLP_PARAMS], loss [1]) of the mean squared error over all rows."""
+    import torch
+    grad = torch.empty(MLP_PARAMS, dtype=torch.float32, device=features.device)
+    loss = torch.empty(1, dtype=torch.float32, device=features.device)
+    _check(_lib.orbit_mlp_grad(weights.data_ptr(), features.data_ptr(), _ptr(targets),
+                               _ptr(steps), features.shape[0], grad.data_ptr(), loss.data_ptr(),
+                               _stream_ptr(stream)), "orbit_mlp_grad")
+    return grad, loss
+
+
+def mlp_train(weights, features, steps, iters=300, batch=4096, lr=3e-3, seed=7, stream=None):
+    """Adam on log2(1 + steps) targets, weights updated in place; returns
+    the last mini-batch loss (synchronises)."""
+    import torch
+    state = torch.empty(3 * MLP_PARAMS + 1, dtype=torch.float32, device=features.device)
+    _check(_lib.orbit_mlp_train(features.data_ptr(), steps.data_ptr(), features.shape[0],
+                                weights.data_ptr(), state.data_ptr(), iters, batch, lr, seed,
+                                _stream_ptr(stream)), "orbit_mlp_train")
+    return float(state[-1].item())
+
+
 def raw_count_ex(rp, ci, n, m, k_max, counts, ws, ws_bytes, flags=0, stream=None):
     """Direct call of orbit_count_ex with explicit arguments (tests)."""
     need = ctypes.c_uint64(0)
-    o = _Opts(flags, 0)
+    o = _Opts(flags, 0, 0, 0, None, None, None)
     st = _lib.orbit_count_ex(ctypes.c_void_p(rp), ctypes.c_void_p(ci), n, m, k_max,
                              ctypes.c_void_p(counts), ctypes.c_void_p(ws), ws_bytes,
                              ctypes.byref(need), _stream_ptr(stream), ctypes.byref(o))

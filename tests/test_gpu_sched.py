@@ -1,0 +1,162 @@
+"""Source schedules and the cost model, on the GPU through the C ABI.
+
+The schedule only reorders sources, so the counts stay bit-exact against the
+oracle under every schedule.  The cost model is fp32; its gradient and
+predictions are checked against a float64 numpy transcription of the same
+network (relative tolerance 1e-4: fp32 sums of at most a few thousand terms).
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1911_10616_amd import graphgen as gg
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def orbit():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1911_10616_amd import orbit as o
+    return o
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _graphs():
+    return [
+        ("chunglu_perm", lambda: gg.relabel(*gg.chung_lu(600, 8.0, 2.1, 80.0, 2400, 11), 5)),
+        ("ba", lambda: gg.barabasi_albert(120, 4, 21)),
+        ("er", lambda: gg.erdos_renyi(50, 0.3, 31)),
+        ("k9", lambda: gg.complete(9)),
+    ]
+
+
+def _run(orbit, rp, ci, schedule, w=None):
+    import torch
+    n = len(rp) - 1
+    feat = torch.full((max(n, 1), 3), float("nan"), dtype=torch.float32, device="cuda")
+    steps = torch.full((max(n, 1),), 12345, dtype=torch.int64, device="cuda")
+    c = orbit.Counter(rp, ci, 5, schedule=schedule, mlp_weights=w, features_out=feat,
+                      steps_out=steps, num_wg=5)
+    got = c.run().cpu().numpy().view(np.uint64)
+    return got, feat[:n].cpu().numpy(), steps[:n].cpu().numpy().view(np.uint64)
+
+
+@pytest.mark.parametrize("name,make", _graphs(), ids=[g[0] for g in _graphs()])
+def test_counts_identical_under_every_schedule(orbit, name, make):
+    rp, ci = make()
+    _say("schedules on", name, len(rp) - 1, ci.size // 2)
+    ref = oracle.induced_counts(rp, ci, threads=8)
+    w = orbit.mlp_init(seed=3)
+    first_steps = None
+    for sched in ("id", "static", "mlp"):
+        got, feat, steps = _run(orbit, rp, ci, sched, w)
+        np.testing.assert_array_equal(got, ref, err_msg=sched)
+        assert np.isfinite(feat).all()
+        # per-source step totals do not depend on the order of sources
+        if first_steps is None:
+            first_steps = steps
+        np.testing.assert_array_equal(steps, first_steps, err_msg=sched)
+
+
+def test_features(orbit):
+    rp, ci = gg.relabel(*gg.chung_lu(2000, 10.0, 2.1, 150.0, 10000, 41), 6)
+    _, feat, _ = _run(orbit, rp, ci, "id")
+    deg = np.diff(rp).astype(np.float64)
+    np.testing.assert_allclose(feat[:, 2], np.log2(1 + deg), rtol=1e-6)
+    dplus = np.rint(np.exp2(feat[:, 0].astype(np.float64)) - 1)
+    assert dplus.sum() == ci.size // 2  # every edge oriented exactly once
+    assert (dplus <= deg).all()
+    s = np.rint(np.exp2(feat[:, 1].astype(np.float64)) - 1)
+    # sum_u sum_{w in N+(u)} d+(w) = sum_w d+(w) d-(w)
+    assert s.sum() == (dplus * (deg - dplus)).sum()
+
+
+def _np_forward(w, X):
+    W1 = w[:96].reshape(32, 3); b1 = w[96:128]; W2 = w[128:1152].reshape(32, 32)
+    b2 = w[1152:1184]; W3 = w[1184:1216]; b3 = w[1216]
+    z1 = X @ W1.T + b1; h1 = np.maximum(z1, 0)
+    z2 = h1 @ W2.T + b2; h2 = np.maximum(z2, 0)
+    return h2 @ W3 + b3, (z1, h1, z2, h2)
+
+
+def _np_grad(w, X, T):
+    W2 = w[128:1152].reshape(32, 32); W3 = w[1184:1216]
+    y, (z1, h1, z2, h2) = _np_forward(w, X)
+    dy = 2 * (y - T) / len(X)
+    d2 = dy[:, None] * W3[None, :] * (z2 > 0)
+    d1 = (d2 @ W2) * (z1 > 0)
+    g = np.zeros_like(w)
+    g[:96] = (d1.T @ X).ravel(); g[96:128] = d1.sum(0)
+    g[128:1152] = (d2.T @ h1).ravel(); g[1152:1184] = d2.sum(0)
+    g[1184:1216] = h2.T @ dy; g[1216] = dy.sum()
+    return g, ((y - T) ** 2).mean()
+
+
+def _training_set(orbit):
+    rp, ci = gg.relabel(*gg.chung_lu(3000, 10.0, 2.1, 200.0, 15000, 51), 7)
+    _, feat, steps = _run(orbit, rp, ci, "id")
+    return feat, steps
+
+
+def test_mlp_predict_and_grad_match_float64(orbit):
+    import torch
+    feat, steps = _training_set(orbit)
+    w = orbit.mlp_init(seed=9)
+    wn = w.cpu().numpy().astype(np.float64)
+    X = feat.astype(np.float64)
+    T = np.log2(1 + steps.astype(np.float64))
+    fd = torch.from_numpy(feat).cuda()
+    pred = orbit.mlp_predict(w, fd).cpu().numpy()
+    yref = _np_forward(wn, X)[0]
+    np.testing.assert_allclose(pred, yref, rtol=1e-4, atol=1e-4 * np.abs(yref).max())
+    gref, lref = _np_grad(wn, X, T)
+    sd = torch.from_numpy(steps.view(np.int64)).cuda()
+    g, loss = orbit.mlp_grad(w, fd, steps=sd)
+    np.testing.assert_allclose(g.cpu().numpy(), gref, rtol=1e-4, atol=1e-4 * np.abs(gref).max())
+    assert abs(float(loss.item()) - lref) <= 1e-4 * lref
+    # float targets give the same result
+    g2, loss2 = orbit.mlp_grad(w, fd, targets=torch.from_numpy(T.astype(np.float32)).cuda())
+    np.testing.assert_allclose(g2.cpu().numpy(), gref, rtol=1e-4, atol=1e-4 * np.abs(gref).max())
+
+
+def test_mlp_training_reduces_loss(orbit):
+    import torch
+    feat, steps = _training_set(orbit)
+    X = feat.astype(np.float64)
+    T = np.log2(1 + steps.astype(np.float64))
+    w = orbit.mlp_init(seed=4)
+    before = _np_grad(w.cpu().numpy().astype(np.float64), X, T)[1]
+    orbit.mlp_train(w, torch.from_numpy(feat).cuda(), torch.from_numpy(steps.view(np.int64)).cuda(),
+                    iters=400, batch=1024, lr=3e-3, seed=2)
+    after = _np_grad(w.cpu().numpy().astype(np.float64), X, T)[1]
+    _say("mlp loss", before, "->", after)
+    assert after < 0.25 * before
+
+
+def test_schedule_argument_errors(orbit):
+    import torch
+    rp, ci = gg.complete(5)
+    rpd = torch.from_numpy(rp.view(np.int32)).cuda()
+    cid = torch.from_numpy(ci.view(np.int32)).cuda()
+    out = torch.empty((5, 73), dtype=torch.int64, device="cuda")
+    ws = torch.empty(orbit.workspace_bytes(rp, ci, 5), dtype=torch.uint8, device="cuda")
+    lib = orbit._lib
+    w = orbit.mlp_init()
+    for sched, reserved, wp, want in ((3, 0, w.data_ptr(), -1), (2, 0, None, -1),
+                                      (0, 1, None, -1), (2, 0, w.data_ptr(), 0)):
+        o = orbit._Opts(0, 0, sched, reserved, wp, None, None)
+        need = ctypes.c_uint64(0)
+        st = lib.orbit_count_ex(ctypes.c_void_p(rpd.data_ptr()), ctypes.c_void_p(cid.data_ptr()),
+                                5, 10, 5, ctypes.c_void_p(out.data_ptr()),
+                                ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.byref(need),
+                                None, ctypes.byref(o))
+        assert st == want, (sched, reserved, st)
+    assert lib.orbit_mlp_train(None, None, 0, None, None, 1, 1, ctypes.c_float(1e-3), 0, None) == -1

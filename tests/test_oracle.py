@@ -308,3 +308,14 @@ def test_transform_structure():
     sign = (-1) ** ((e[None, :] - e[:, None]) % 2)
     Ainv = sign * A
     np.testing.assert_array_equal(A @ Ainv, np.eye(73, dtype=np.int64))
+
+
+def test_relabel_permutes_counts():
+    """Isomorphism invariance: counts of a relabelled graph are the counts
+    of the original, moved with the vertices."""
+    rp, ci = gg.barabasi_albert(30, 3, 77)
+    rp2, ci2 = gg.relabel(rp, ci, 5)
+    perm = np.random.Generator(np.random.PCG64(5)).permutation(len(rp) - 1)
+    a = oracle.induced_counts(rp, ci)
+    b = oracle.induced_counts(rp2, ci2)
+    np.testing.assert_array_equal(b[perm], a)
