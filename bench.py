@@ -109,8 +109,10 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="chunglu1m", choices=sorted(WORKLOADS))
-    ap.add_argument("--schedule", default="id", choices=("id", "static", "mlp"),
+    ap.add_argument("--schedule", default="mlp", choices=("id", "static", "mlp"),
                     help="order of sources in the per-source kernels")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the one-step run with the static schedule")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -159,6 +161,20 @@ def main():
     el = time.perf_counter() - t0
     stats = orbit.last_stats()
     ms_step = 1000.0 * el / args.steps
+    compare = None
+    if not args.no_compare and args.schedule != "static":
+        # the plain static-threshold schedule on the same graph, one step
+        del counter
+        torch.cuda.empty_cache()
+        cs = orbit.Counter(rp, ci, k_max=5, schedule="static")
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        cs.run()
+        torch.cuda.synchronize()
+        st_ms = 1000.0 * (time.perf_counter() - t1)
+        compare = {"schedule": "static", "ms_per_step": round(st_ms, 3),
+                   "speedup_of_" + args.schedule: round(st_ms / ms_step, 4)}
+        del cs
     value = m * args.steps / el
     phases = {k: v / args.steps for k, v in phases.items()}
 
@@ -194,6 +210,8 @@ def main():
         "phases_ms": {k: round(v, 3) for k, v in phases.items()},
         "work": stats,
     }
+    if compare is not None:
+        line["vs_static_schedule"] = compare
     if train_loss is not None:
         line["cost_model"] = {"trained_on": TRAIN_WORKLOAD, "mse_log2_steps": round(train_loss, 4)}
     if not args.no_cpu_baseline and rank == 0:
