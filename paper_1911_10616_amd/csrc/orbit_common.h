@@ -96,6 +96,10 @@ __device__ inline u32 bfind(const u32 *a, u32 len, u32 key) {
     return (i < len && a[i] == key) ? i : UNSET;
 }
 
+__device__ inline unsigned char *align256(unsigned char *p) {
+    return (unsigned char *)(((uintptr_t)p + 255) & ~(uintptr_t)255);
+}
+
 __device__ inline void atomic_add_u64(u64 *p, u64 v) {
     if (v) atomicAdd(p, v);
 }

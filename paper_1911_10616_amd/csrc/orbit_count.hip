@@ -95,6 +95,125 @@ __global__ void k_tl_fill(const u32 *src, const u32 *ci, const u32 *rev, u64 ntr
     }
 }
 
+// Sorting the per-edge triangle lists by third vertex.  Within one list the
+// third vertices are distinct, and both components of an entry grow with
+// the third vertex's id (neighbour lists are ascending), so ordering by the
+// first component orders the list by third vertex.  Lists of up to 64
+// entries are sorted by one wave in registers (bitonic network over lanes);
+// longer ones are queued for k_tl_sort_wg.
+#ifndef TL_SORT_LDS
+#define TL_SORT_LDS 4096
+#endif
+__device__ inline u64 tl_key(uint2 e) { return ((u64)e.x << 32) | e.y; }
+__device__ inline uint2 tl_unkey(u64 k) { return make_uint2((u32)(k >> 32), (u32)k); }
+
+__global__ void k_tl_sort_small(const u32 *src, const u32 *ci, const u32 *T, const u64 *tl_ptr,
+                                uint2 *tl, u64 M2, u32 *queue, u32 *qlen) {
+    const u32 lane = lane_id();
+    for (u64 s = GWAVE; s < M2; s += NWAVES) {
+        if (src[s] > ci[s]) continue;  // the list lives at the canonical slot
+        const u32 L = T[s];
+        if (L < 2) continue;
+        if (L > WAVE) {
+            if (lane == 0) queue[atomicAdd(qlen, 1u)] = (u32)s;
+            continue;
+        }
+        uint2 *p = tl + tl_ptr[s];
+        u64 key = ~0ull;
+        if (lane < L) key = tl_key(p[lane]);
+        for (u32 k = 2; k <= WAVE; k <<= 1) {
+            for (u32 j = k >> 1; j > 0; j >>= 1) {
+                const u64 other = __shfl_xor(key, (int)j, WAVE);
+                const bool keep_min = ((lane & j) == 0) == ((lane & k) == 0);
+                key = keep_min ? (key < other ? key : other) : (key > other ? key : other);
+            }
+        }
+        if (lane < L) p[lane] = tl_unkey(key);
+    }
+}
+
+// One workgroup per queued list.  Up to TL_SORT_LDS entries: bitonic sort in
+// LDS.  Longer lists (both ends then have degree > TL_SORT_LDS): counting
+// sort over positions in the shorter of the two neighbour lists -- a bitmap
+// of occupied positions and the other component stored at its position in
+// the workgroup's scratch, then ranks from a scan of the bitmap's popcounts.
+__global__ void __launch_bounds__(WG) k_tl_sort_wg(const u32 *rp, const u32 *src, const u32 *ci,
+                                                  const u32 *T, const u64 *tl_ptr, uint2 *tl,
+                                                  const u32 *queue, const u32 *qlen,
+                                                  unsigned char *scratch, u64 stride, u32 n) {
+    __shared__ u64 sk[TL_SORT_LDS];
+    __shared__ u32 part[WG];
+    u32 *oth = (u32 *)(scratch + (u64)blockIdx.x * stride);          // n entries
+    u32 *bm = (u32 *)align256((unsigned char *)(oth + n));           // ceil(n/32) words
+    const u32 cnt = *qlen;
+    for (u32 qi = blockIdx.x; qi < cnt; qi += gridDim.x) {
+        const u32 s = queue[qi];
+        const u32 L = T[s];
+        uint2 *p = tl + tl_ptr[s];
+        if (L <= TL_SORT_LDS) {
+            u32 P = 128;
+            while (P < L) P <<= 1;
+            for (u32 i = threadIdx.x; i < P; i += WG) sk[i] = i < L ? tl_key(p[i]) : ~0ull;
+            __syncthreads();
+            for (u32 k = 2; k <= P; k <<= 1) {
+                for (u32 j = k >> 1; j > 0; j >>= 1) {
+                    for (u32 i = threadIdx.x; i < P; i += WG) {
+                        const u32 ij = i ^ j;
+                        if (ij > i) {
+                            const u64 x = sk[i], y = sk[ij];
+                            const bool asc = (i & k) == 0;
+                            if ((x > y) == asc) { sk[i] = y; sk[ij] = x; }
+                        }
+                    }
+                    __syncthreads();
+                }
+            }
+            for (u32 i = threadIdx.x; i < L; i += WG) p[i] = tl_unkey(sk[i]);
+            __syncthreads();
+            continue;
+        }
+        const u32 lo = src[s], hi = ci[s];
+        const u32 dlo = rp[lo + 1] - rp[lo], dhi = rp[hi + 1] - rp[hi];
+        const bool by_lo = dlo <= dhi;
+        const u32 base = by_lo ? rp[lo] : rp[hi];
+        const u32 D = by_lo ? dlo : dhi;
+        const u32 nw = (D + 31) / 32;
+        for (u32 w = threadIdx.x; w < nw; w += WG) bm[w] = 0;
+        __syncthreads();
+        for (u32 i = threadIdx.x; i < L; i += WG) {
+            const uint2 e = p[i];
+            const u32 pos = (by_lo ? e.x : e.y) - base;
+            atomicOr(&bm[pos >> 5], 1u << (pos & 31));
+            oth[pos] = by_lo ? e.y : e.x;
+        }
+        __syncthreads();
+        // each thread owns a contiguous run of bitmap words
+        const u32 per = (nw + WG - 1) / WG;
+        const u32 w0 = threadIdx.x * per, w1 = w0 + per < nw ? w0 + per : nw;
+        u32 c = 0;
+        for (u32 w = w0; w < w1; w++) c += __popc(bm[w]);
+        part[threadIdx.x] = c;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            u32 run = 0;
+            for (u32 t = 0; t < WG; t++) { const u32 v = part[t]; part[t] = run; run += v; }
+        }
+        __syncthreads();
+        u32 r = part[threadIdx.x];
+        for (u32 w = w0; w < w1; w++) {
+            u32 bits = bm[w];
+            while (bits) {
+                const u32 b = __ffs(bits) - 1;
+                bits &= bits - 1;
+                const u32 pos = w * 32 + b;
+                const u32 mine = base + pos, other = oth[pos];
+                p[r++] = by_lo ? make_uint2(mine, other) : make_uint2(other, mine);
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // Triangle list of slot s = (u,v) as (slot(u,x), slot(v,x)) pairs.
 struct TLView {
     const uint2 *p;
@@ -172,10 +291,6 @@ __device__ inline u64 block_sum_u64(u64 v, u64 *sh) {
     u64 t = 0;
     for (int w = 0; w < WAVES_PER_WG; w++) t += sh[w];
     return t;
-}
-
-__device__ inline unsigned char *align256(unsigned char *p) {
-    return (unsigned char *)(((uintptr_t)p + 255) & ~(uintptr_t)255);
 }
 
 // ---- 4-cycles (Chiba-Nishizeki).  For every top vertex x: the wedges
@@ -480,6 +595,10 @@ __global__ void k_tri_k4terms(const u32 *src, const u32 *ci, const u32 *T, u64 n
 //     the sum of Q over the arcs into y).
 // The remaining subtractions (36: -N13, 51: -2 N12, 62: -N13) happen in the
 // per-vertex combine.
+// wheel maps of up to this many positions live in LDS (per wave)
+#ifndef PAIR_KMAP_LDS
+#define PAIR_KMAP_LDS 2048
+#endif
 struct PairScratch {
     u32 *S;
     u64 *E, *TA, *TB;
@@ -509,9 +628,12 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
     __shared__ u32 sh_src, sh_nt, sh_next;
     __shared__ u32 sh_ntk[WAVES_PER_WG];
     __shared__ u64 sh_red[WAVES_PER_WG];
+    __shared__ u32 l_k[WAVES_PER_WG][PAIR_KMAP_LDS];
+    __shared__ unsigned short l_tk[WAVES_PER_WG][PAIR_KMAP_LDS];
     PairScratch P = pair_scratch(scratch + (u64)blockIdx.x * stride, n);
     u32 *Kw = P.K + (u64)wave_in_wg() * n;
     u32 *tkw = P.tk + (u64)wave_in_wg() * n;
+    for (u32 i = threadIdx.x; i < WAVES_PER_WG * PAIR_KMAP_LDS; i += WG) (&l_k[0][0])[i] = 0;
     for (;;) {
         const u32 a = next_source(work, &sh_src, order, n);
         if (a >= n) break;
@@ -540,34 +662,78 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
         __syncthreads();
         if (threadIdx.x == 0) sh_next = 0;
         __syncthreads();
-        // diamonds with tip a, chord (y,z), y < z, other tip b > a
+        // wheel maps of the arcs (a, y): K(a,y,b) = |N(a) & N(y) & N(b)| for
+        // b > a, from the diamonds with tip a and chord (y,z) (z in the
+        // triangle list of (a,y), b in the list of (y,z), which is sorted by
+        // third vertex so the part with b > a is found by binary search).
+        // Draining a map gives orbit 68 (C(K,2) to a and b), Q(a,y), the
+        // doubled inner edge count E2(a,b) = sum_y K(a,y,b) = 2 |E(S)|, and
+        // the chord terms of orbit 64: y gets K(a,y,b) (s(a,b) - 2), i.e.
+        // s - 2 per diamond with chord (y,z) -- z gets its share when it is
+        // the arc's end.
+        if (lane_id() == 0) sh_ntk[wave_in_wg()] = 0;
+        u64 l68 = 0;
         wave_loop(&sh_next, da, [&](u32 iy) {
             const u32 say = ba + iy, y = ci[say];
             if (T[say] == 0) return;
+            // the map of (a, y) is indexed by b's position in N(y): in LDS
+            // when d(y) fits, else in the wave's global map
+            const u32 by = rp[y], dy = rp[y + 1] - by;
+            const bool inl = dy <= PAIR_KMAP_LDS;
+            u32 *kc = inl ? l_k[wave_in_wg()] : Kw;
+            unsigned short *tl_l = l_tk[wave_in_wg()];
             TLView tv = tl_view(say, src, ci, rev, T, tl_ptr, tl);
-            u64 accy = 0;
+            u32 *ntk = &sh_ntk[wave_in_wg()];
             for (u32 k = 0; k < tv.len; k++) {
-                uint2 ez = tv.get(k);  // (slot(a,z), slot(y,z))
-                const u32 z = ci[ez.x];
-                if (z <= y) continue;
-                TLView tw = tl_view(ez.y, src, ci, rev, T, tl_ptr, tl);
-                u64 chord = 0;
-                for (u32 q = lane_id(); q < tw.len; q += WAVE) {
-                    uint2 eb = tw.get(q);  // (slot(y,b), slot(z,b))
-                    const u32 b = ci[eb.x];
-                    nsteps++;
-                    if (b <= a) continue;
-                    atomicAdd(&P.E[b], 1ull);
-                    chord += (u64)P.S[b] - 2;
+                const uint2 ez = tv.get(k);  // (slot(a,z), slot(y,z))
+                const TLView tw = tl_view(ez.y, src, ci, rev, T, tl_ptr, tl);
+                // first entry whose third vertex exceeds a
+                u32 lo = 0, hi = tw.len;
+                while (lo < hi) {
+                    const u32 mid = (lo + hi) >> 1;
+                    if (ci[tw.get(mid).x] <= a) lo = mid + 1; else hi = mid;
                 }
-                chord = wave_sum_u64(chord);
-                if (lane_id() == 0) atomic_add_u64(&NI(z, 64), chord);
-                accy += chord;
+                for (u32 q = lo + lane_id(); q < tw.len; q += WAVE) {
+                    const u32 pos = tw.get(q).x - by;  // slot(y,b) - rp[y]
+                    nsteps++;
+                    u32 old = atomicAdd(&kc[pos], 1u);
+                    if (old == 0) {
+                        const u32 t = atomicAdd(ntk, 1u);
+                        if (inl) tl_l[t] = (unsigned short)pos; else tkw[t] = pos;
+                    }
+                }
             }
-            if (lane_id() == 0) atomic_add_u64(&NI(y, 64), accy);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            const u32 m = *ntk;
+            u64 q = 0, c64 = 0;
+            for (u32 t = lane_id(); t < m; t += WAVE) {
+                const u32 pos = inl ? (u32)tl_l[t] : tkw[t];
+                const u32 kab = atomicExch(&kc[pos], 0u);
+                const u32 b = ci[by + pos];
+                const u64 v = c2((i64)kab);
+                q += v;
+                atomic_add_u64(&NI(b, 68), v);
+                atomicAdd(&P.E[b], (u64)kab);
+                c64 += (u64)kab * ((u64)P.S[b] - 2);
+            }
+            q = wave_sum_u64(q);
+            c64 = wave_sum_u64(c64);
+            if (lane_id() == 0) {
+                Q[say] = q;
+                atomic_add_u64(&NI(y, 64), c64);
+                *ntk = 0;
+            }
+            l68 += q;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
         });
         __syncthreads();
-        // pair terms
+        // l68 is uniform within each wave (computed from wave sums)
+        if (lane_id() == 0) atomic_add_u64(&NI(a, 68), l68);
+        // pair terms (P.E holds 2 e)
         const u32 nt = sh_nt;
         u64 l36 = 0, l50 = 0, l51 = 0, l63 = 0;
         for (u32 t = threadIdx.x; t < nt; t += WG) {
@@ -575,7 +741,7 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
             const u64 s = P.S[b];
             if (s < 2) continue;
             const u64 adj = P.mark[b];
-            const u64 e = P.E[b];
+            const u64 e = P.E[b] >> 1;
             const u64 cs2 = c2((i64)s), cs3 = c3((i64)s);
             l36 += cs2 * ((u64)deg[b] - 2);
             l50 += cs3;
@@ -598,9 +764,7 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
             sh_next = 0;
         }
         __syncthreads();
-        // centre terms, then the wheel maps of (a, y) with a per-wave map
-        if (lane_id() == 0) sh_ntk[wave_in_wg()] = 0;
-        u64 l68 = 0;
+        // centre terms
         wave_loop(&sh_next, da, [&](u32 iy) {
             const u32 say = ba + iy, y = ci[say];
             const u32 by = rp[y], ey = rp[y + 1];
@@ -612,7 +776,7 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
                 nsteps++;
                 if (sb >= 2) {
                     a49 += c2((i64)sb - 1);
-                    a62 += P.E[b];
+                    a62 += P.E[b] >> 1;
                 }
             }
             a49 = wave_sum_u64(a49);
@@ -621,44 +785,8 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
                 atomic_add_u64(&NI(y, 49), a49);
                 atomic_add_u64(&NI(y, 62), a62);
             }
-            if (T[say] < 2) return;
-            TLView tv = tl_view(say, src, ci, rev, T, tl_ptr, tl);
-            u32 *ntk = &sh_ntk[wave_in_wg()];
-            for (u32 k = 0; k < tv.len; k++) {
-                uint2 ez = tv.get(k);
-                TLView tw = tl_view(ez.y, src, ci, rev, T, tl_ptr, tl);
-                for (u32 q = lane_id(); q < tw.len; q += WAVE) {
-                    const u32 b = ci[tw.get(q).x];
-                    nsteps++;
-                    if (b <= a) continue;
-                    u32 old = atomicAdd(&Kw[b], 1u);
-                    if (old == 0) tkw[atomicAdd(ntk, 1u)] = b;
-                }
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-            const u32 m = *ntk;
-            u64 q = 0;
-            for (u32 t = lane_id(); t < m; t += WAVE) {
-                const u32 b = tkw[t];
-                const u64 v = c2((i64)atomicExch(&Kw[b], 0u));
-                q += v;
-                atomic_add_u64(&NI(b, 68), v);
-            }
-            q = wave_sum_u64(q);
-            if (lane_id() == 0) {
-                Q[say] = q;
-                *ntk = 0;
-            }
-            l68 += q;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
         });
         __syncthreads();
-        // l68 is uniform within each wave (computed from wave sums)
-        if (lane_id() == 0) atomic_add_u64(&NI(a, 68), l68);
         for (u32 t = threadIdx.x; t < nt; t += WG) {
             const u32 b = P.touched[t];
             P.S[b] = 0; P.E[b] = 0; P.TA[b] = 0; P.TB[b] = 0;

@@ -420,6 +420,16 @@ int count_impl(const u32 *rp, const u32 *ci, u32 n, u64 m, int k_max, u64 *count
                                                     tlptr, tlcur, tl);
         k_edge_e7e9<<<grid_for(M2, WG), WG, 0, s>>>(src, ci, rev, deg, T, tlptr, tl, M2, E7, E9);
         HCHK(hipGetLastError());
+        if (k_max >= 5) {
+            // lists sorted by third vertex for the pair sweep; the queue of
+            // long lists reuses the (now free) list-length array, and the
+            // long-list sort uses the per-source scratch before it is zeroed
+            u32 *qlen = st->work + 15;
+            k_tl_sort_small<<<grid_waves(M2), WG, 0, s>>>(src, ci, T, tlptr, tl, M2, tllen, qlen);
+            k_tl_sort_wg<<<L.nwg, WG, 0, s>>>(rp, src, ci, T, tlptr, tl, tllen, qlen, scratch,
+                                              L.stride, n);
+            HCHK(hipGetLastError());
+        }
     }
     tm.mark("tri_lists");
     k_vert0<<<grid_waves(n), WG, 0, s>>>(rp, ci, deg, T, n, Tv, N1);

@@ -101,6 +101,55 @@ def test_hub_larger_than_lds_tile(orbit):
     assert (np.delete(got, [0, 3, 14, 72], axis=1) == 0).all()
 
 
+def _book(k):
+    """k triangles sharing the edge (0, 1): spine 0, 1; pages 2 .. k+1."""
+    pages = np.arange(2, k + 2)
+    u = np.concatenate([[0], np.zeros(k, np.int64), np.ones(k, np.int64)])
+    v = np.concatenate([[1], pages, pages])
+    return gg.csr_from_edges(k + 2, u, v)
+
+
+def _book_counts(k):
+    """Induced counts of the book with k pages, from the oracle on books with
+    4..8 pages: every count of a spine vertex or a page is a sum of
+    C(k, j) c_j (j <= 4) over the pages a 2..5-vertex subset takes, hence a
+    polynomial of degree <= 4 in k, fixed exactly by five values."""
+    from fractions import Fraction
+    ks = [4, 5, 6, 7, 8]
+    spine = [oracle.induced_counts(*_book(j))[0].astype(object) for j in ks]
+    page = [oracle.induced_counts(*_book(j))[2].astype(object) for j in ks]
+    def interp(rows):
+        out = []
+        for o in range(73):
+            tot = Fraction(0)
+            for i, xi in enumerate(ks):
+                term = Fraction(int(rows[i][o]))
+                for j, xj in enumerate(ks):
+                    if j != i:
+                        term *= Fraction(k - xj, xi - xj)
+                tot += term
+            assert tot.denominator == 1
+            out.append(int(tot) % (1 << 64))
+        return np.array(out, dtype=np.uint64)
+    exp = np.empty((k + 2, 73), dtype=np.uint64)
+    exp[0] = exp[1] = interp(spine)
+    exp[2:] = interp(page)
+    return exp
+
+
+@pytest.mark.parametrize("k", [70, 300, 5000])
+def test_book_long_triangle_lists(orbit, k):
+    """One edge in k triangles: its triangle list is sorted in registers
+    (<= 64), in LDS (<= 4096) or by the bitmap counting sort (> 4096)."""
+    _say("book", k)
+    rp, ci = _book(k)
+    exp = _book_counts(k)
+    np.testing.assert_array_equal(orbit.count(rp, ci, 5), exp)
+    rp2, ci2 = gg.relabel(rp, ci, 77)
+    perm = np.random.Generator(np.random.PCG64(77)).permutation(k + 2)
+    np.testing.assert_array_equal(orbit.count(rp2, ci2, 5)[perm], exp)
+
+
 def test_er2000_full(orbit):
     """The ER(n=2000, p=0.005) workload, every vertex and orbit."""
     rp, ci = gg.workload("er2000")
