@@ -64,6 +64,8 @@ extern "C" {
 #define ORB_E_WORKSPACE (-7)    /* workspace too small: see *ws_required */
 #define ORB_E_DEVICE (-8)       /* a HIP call failed */
 #define ORB_E_INTERNAL (-9)     /* internal consistency check failed */
+#define ORB_E_BATCH (-10)       /* batched input: graph offsets not 0..n and non-decreasing,
+                                   or an edge joining two graphs */
 
 /* option flags */
 #define ORB_NONINDUCED 0x1u /* return non-induced counts DM(u, theta) */
@@ -118,6 +120,39 @@ int orbit_workspace_query(const uint32_t *row_ptr, const uint32_t *col_idx, uint
 int orbit_count_ex(const uint32_t *row_ptr, const uint32_t *col_idx, uint32_t n, uint64_t m,
                    int k_max, uint64_t *counts, void *workspace, uint64_t ws_bytes,
                    uint64_t *ws_required, void *stream, const orb_opts *opts);
+
+/* ---- many small graphs in one call.
+ * The batch is the disjoint union of num_graphs graphs stored as one CSR
+ * over global vertex ids: graph g owns vertices vptr[g] .. vptr[g+1]-1
+ * (vptr: DEVICE array of num_graphs+1 uint64, vptr[0] = 0, non-decreasing,
+ * vptr[num_graphs] = n; empty graphs allowed) and every edge joins two
+ * vertices of the same graph (else ORB_E_BATCH).  The counts of graph g are
+ * rows vptr[g] .. vptr[g+1]-1 of counts -- the counts of each graph on its
+ * own, since every orbit lives inside one connected component.  The
+ * per-source maps are indexed within the source's graph, so the scratch
+ * scales with the largest graph instead of n.  Otherwise as orbit_count_ex. */
+int orbit_count_batched(const uint64_t *vptr, uint32_t num_graphs, const uint32_t *row_ptr,
+                        const uint32_t *col_idx, uint32_t n, uint64_t m, int k_max,
+                        uint64_t *counts, void *workspace, uint64_t ws_bytes,
+                        uint64_t *ws_required, void *stream, const orb_opts *opts);
+
+/* Workspace size of orbit_count_batched (validates the batch on the device). */
+int orbit_workspace_query_batched(const uint64_t *vptr, uint32_t num_graphs,
+                                  const uint32_t *row_ptr, const uint32_t *col_idx, uint32_t n,
+                                  uint64_t m, int k_max, void *stream, const orb_opts *opts,
+                                  uint64_t *bytes);
+
+/* Autotuner: runs the count (batched when vptr is not NULL, else one graph)
+ * once per candidate workgroup count and schedule (id, static thresholds,
+ * and the cost model when base->mlp_weights is set), timed with HIP events,
+ * and returns in *best the options (base's flags, the fastest num_wg and
+ * schedule) and in *best_ms its GPU time.  Candidates whose workspace does
+ * not fit ws_bytes are skipped.  counts receives the last run's counts. */
+int orbit_autotune(const uint64_t *vptr, uint32_t num_graphs, const uint32_t *row_ptr,
+                   const uint32_t *col_idx, uint32_t n, uint64_t m, int k_max, uint64_t *counts,
+                   void *workspace, uint64_t ws_bytes, void *stream, const orb_opts *base,
+                   const uint32_t *nwg_candidates, int num_candidates, orb_opts *best,
+                   float *best_ms);
 
 /* Human-readable text of a status code (static storage). */
 const char *orbit_strerror(int status);

@@ -21,6 +21,8 @@ typedef long long i64;
 #define ERRB_ASYM 0x10u
 #define ERRB_ROWPTR 0x20u
 #define ERRB_INTERNAL 0x40u
+#define ERRB_CROSS 0x80u     // batched input: an edge joins two graphs
+#define ERRB_VPTR 0x100u     // batched input: malformed graph offsets
 
 // Small block of device state shared by the phases of one call.
 struct DevState {
@@ -32,7 +34,7 @@ struct DevState {
     u32 alive;      // peeling: vertices not yet removed
     u32 minalive;   // peeling: smallest remaining degree seen by a scan
     u32 maxlevel;   // peeling: largest level at which a vertex was removed
-    u32 pad0;
+    u32 gmax;       // batched input: largest graph (vertices)
     u32 work[16];   // dynamic work counters of the per-source kernels
     u64 ntri;       // number of triangles
     u64 scan_total; // total of the last exclusive scan

@@ -140,11 +140,11 @@ __global__ void k_tl_sort_small(const u32 *src, const u32 *ci, const u32 *T, con
 __global__ void __launch_bounds__(WG) k_tl_sort_wg(const u32 *rp, const u32 *src, const u32 *ci,
                                                   const u32 *T, const u64 *tl_ptr, uint2 *tl,
                                                   const u32 *queue, const u32 *qlen,
-                                                  unsigned char *scratch, u64 stride, u32 n) {
+                                                  unsigned char *scratch, u64 stride, u32 mapn) {
     __shared__ u64 sk[TL_SORT_LDS];
     __shared__ u32 part[WG];
-    u32 *oth = (u32 *)(scratch + (u64)blockIdx.x * stride);          // n entries
-    u32 *bm = (u32 *)align256((unsigned char *)(oth + n));           // ceil(n/32) words
+    u32 *oth = (u32 *)(scratch + (u64)blockIdx.x * stride);          // mapn entries
+    u32 *bm = (u32 *)align256((unsigned char *)(oth + mapn));        // ceil(mapn/32) words
     const u32 cnt = *qlen;
     for (u32 qi = blockIdx.x; qi < cnt; qi += gridDim.x) {
         const u32 s = queue[qi];
@@ -300,16 +300,17 @@ __device__ inline u64 block_sum_u64(u64 v, u64 *sh) {
 // Gives C4(u) (orbit 8) and C4(e) (edge orbit E5).
 __global__ void __launch_bounds__(WG) k_c4(const u32 *rp, const u32 *ci, const u32 *rev,
                                           const u64 *key, u32 n, unsigned char *scratch,
-                                          u64 stride, u32 *work, const u32 *order, u64 *C4v,
-                                          u64 *C4e) {
+                                          u64 stride, u32 *work, const u32 *order, u32 mapn,
+                                          const u32 *gbase, u64 *C4v, u64 *C4e) {
     __shared__ u32 sh_src, sh_nt, sh_next;
     __shared__ u64 sh_red[WAVES_PER_WG];
     unsigned char *base = scratch + (u64)blockIdx.x * stride;
     u32 *cnt = (u32 *)base;
-    u32 *touched = (u32 *)align256((unsigned char *)(cnt + n));
+    u32 *touched = (u32 *)align256((unsigned char *)(cnt + mapn));
     for (;;) {
         u32 x = next_source(work, &sh_src, order, n);
         if (x >= n) break;
+        const u32 vb = gbase ? gbase[x] : 0;  // maps are indexed within x's graph
         const u64 kx = key[x];
         const u32 bx = rp[x], dx = rp[x + 1] - bx;
         if (threadIdx.x == 0) { sh_nt = 0; sh_next = 0; }
@@ -320,7 +321,7 @@ __global__ void __launch_bounds__(WG) k_c4(const u32 *rp, const u32 *ci, const u
             for (u32 s = rp[y] + lane_id(); s < rp[y + 1]; s += WAVE) {
                 u32 z = ci[s];
                 if (z != x && key[z] < kx) {
-                    u32 old = atomicAdd(&cnt[z], 1u);
+                    u32 old = atomicAdd(&cnt[z - vb], 1u);
                     if (old == 0) touched[atomicAdd(&sh_nt, 1u)] = z;
                 }
             }
@@ -330,7 +331,7 @@ __global__ void __launch_bounds__(WG) k_c4(const u32 *rp, const u32 *ci, const u
         u64 loc = 0;
         for (u32 t = threadIdx.x; t < nt; t += WG) {
             u32 z = touched[t];
-            u64 v = c2(cnt[z]);
+            u64 v = c2(cnt[z - vb]);
             loc += v;
             atomic_add_u64(&C4v[z], v);
         }
@@ -345,7 +346,7 @@ __global__ void __launch_bounds__(WG) k_c4(const u32 *rp, const u32 *ci, const u
             for (u32 s = rp[y] + lane_id(); s < rp[y + 1]; s += WAVE) {
                 u32 z = ci[s];
                 if (z != x && key[z] < kx) {
-                    u32 c = cnt[z];
+                    u32 c = cnt[z - vb];
                     if (c > 1) {
                         acc += c - 1;
                         atomicAdd(&C4e[s], (u64)(c - 1));
@@ -361,7 +362,7 @@ __global__ void __launch_bounds__(WG) k_c4(const u32 *rp, const u32 *ci, const u
             }
         });
         __syncthreads();
-        for (u32 t = threadIdx.x; t < nt; t += WG) cnt[touched[t]] = 0;
+        for (u32 t = threadIdx.x; t < nt; t += WG) cnt[touched[t] - vb] = 0;
     }
 }
 
@@ -624,24 +625,26 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
                                              const u32 *rev, const u32 *deg, const u32 *T,
                                              const u64 *tl_ptr, const uint2 *tl, u32 n,
                                              unsigned char *scratch, u64 stride, u32 *work,
-                                             const u32 *order, u64 *steps, u64 *Q, u64 *ni) {
+                                             const u32 *order, u32 mapn, const u32 *gbase,
+                                             u64 *steps, u64 *Q, u64 *ni) {
     __shared__ u32 sh_src, sh_nt, sh_next;
     __shared__ u32 sh_ntk[WAVES_PER_WG];
     __shared__ u64 sh_red[WAVES_PER_WG];
     __shared__ u32 l_k[WAVES_PER_WG][PAIR_KMAP_LDS];
     __shared__ unsigned short l_tk[WAVES_PER_WG][PAIR_KMAP_LDS];
-    PairScratch P = pair_scratch(scratch + (u64)blockIdx.x * stride, n);
-    u32 *Kw = P.K + (u64)wave_in_wg() * n;
-    u32 *tkw = P.tk + (u64)wave_in_wg() * n;
+    PairScratch P = pair_scratch(scratch + (u64)blockIdx.x * stride, mapn);
+    u32 *Kw = P.K + (u64)wave_in_wg() * mapn;
+    u32 *tkw = P.tk + (u64)wave_in_wg() * mapn;
     for (u32 i = threadIdx.x; i < WAVES_PER_WG * PAIR_KMAP_LDS; i += WG) (&l_k[0][0])[i] = 0;
     for (;;) {
         const u32 a = next_source(work, &sh_src, order, n);
         if (a >= n) break;
+        const u32 vb = gbase ? gbase[a] : 0;  // maps are indexed within a's graph
         const u32 ba = rp[a], da = rp[a + 1] - ba;
         if (da < 2) continue;
         const u64 dega = da;
         u64 nsteps = 0;  // loop iterations of this thread for this source
-        for (u32 i = threadIdx.x; i < da; i += WG) P.mark[ci[ba + i]] = 1;
+        for (u32 i = threadIdx.x; i < da; i += WG) P.mark[ci[ba + i] - vb] = 1;
         if (threadIdx.x == 0) { sh_nt = 0; sh_next = 0; }
         __syncthreads();
         // wedges a - y - b, b > a
@@ -653,10 +656,10 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
             for (u32 s = st0 + lane_id(); s < ey; s += WAVE) {
                 const u32 b = ci[s];
                 nsteps++;
-                u32 old = atomicAdd(&P.S[b], 1u);
+                u32 old = atomicAdd(&P.S[b - vb], 1u);
                 if (old == 0) P.touched[atomicAdd(&sh_nt, 1u)] = b;
-                atomicAdd(&P.TA[b], tay);
-                atomicAdd(&P.TB[b], (u64)T[s]);
+                atomicAdd(&P.TA[b - vb], tay);
+                atomicAdd(&P.TB[b - vb], (u64)T[s]);
             }
         });
         __syncthreads();
@@ -715,8 +718,8 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
                 const u64 v = c2((i64)kab);
                 q += v;
                 atomic_add_u64(&NI(b, 68), v);
-                atomicAdd(&P.E[b], (u64)kab);
-                c64 += (u64)kab * ((u64)P.S[b] - 2);
+                atomicAdd(&P.E[b - vb], (u64)kab);
+                c64 += (u64)kab * ((u64)P.S[b - vb] - 2);
             }
             q = wave_sum_u64(q);
             c64 = wave_sum_u64(c64);
@@ -738,18 +741,18 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
         u64 l36 = 0, l50 = 0, l51 = 0, l63 = 0;
         for (u32 t = threadIdx.x; t < nt; t += WG) {
             const u32 b = P.touched[t];
-            const u64 s = P.S[b];
+            const u64 s = P.S[b - vb];
             if (s < 2) continue;
-            const u64 adj = P.mark[b];
-            const u64 e = P.E[b] >> 1;
+            const u64 adj = P.mark[b - vb];
+            const u64 e = P.E[b - vb] >> 1;
             const u64 cs2 = c2((i64)s), cs3 = c3((i64)s);
             l36 += cs2 * ((u64)deg[b] - 2);
             l50 += cs3;
-            l51 += (P.TB[b] - adj * s) * (s - 1);
+            l51 += (P.TB[b - vb] - adj * s) * (s - 1);
             l63 += e * (s - 2);
             atomic_add_u64(&NI(b, 36), cs2 * (dega - 2));
             atomic_add_u64(&NI(b, 50), cs3);
-            atomic_add_u64(&NI(b, 51), (P.TA[b] - adj * s) * (s - 1));
+            atomic_add_u64(&NI(b, 51), (P.TA[b - vb] - adj * s) * (s - 1));
             atomic_add_u64(&NI(b, 63), e * (s - 2));
         }
         l36 = block_sum_u64(l36, sh_red);
@@ -772,11 +775,11 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
             u64 a49 = 0, a62 = 0;
             for (u32 s = st0 + lane_id(); s < ey; s += WAVE) {
                 const u32 b = ci[s];
-                const u32 sb = P.S[b];
+                const u32 sb = P.S[b - vb];
                 nsteps++;
                 if (sb >= 2) {
                     a49 += c2((i64)sb - 1);
-                    a62 += P.E[b] >> 1;
+                    a62 += P.E[b - vb] >> 1;
                 }
             }
             a49 = wave_sum_u64(a49);
@@ -789,9 +792,9 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
         __syncthreads();
         for (u32 t = threadIdx.x; t < nt; t += WG) {
             const u32 b = P.touched[t];
-            P.S[b] = 0; P.E[b] = 0; P.TA[b] = 0; P.TB[b] = 0;
+            P.S[b - vb] = 0; P.E[b - vb] = 0; P.TA[b - vb] = 0; P.TB[b - vb] = 0;
         }
-        for (u32 i = threadIdx.x; i < da; i += WG) P.mark[ci[ba + i]] = 0;
+        for (u32 i = threadIdx.x; i < da; i += WG) P.mark[ci[ba + i] - vb] = 0;
         if (steps) {  // per-source work, the training target of the scheduler
             u64 tot = block_sum_u64(nsteps, sh_red);
             if (threadIdx.x == 0) steps[a] += tot;
@@ -833,18 +836,20 @@ __global__ void __launch_bounds__(WG) k_c5(const u32 *rp, const u32 *ci, const u
                                           const u64 *out_ptr, const u32 *out_nbr,
                                           const u32 *out_slot, const u32 *Tin, const u32 *Tmid,
                                           u32 n, unsigned char *scratch, u64 stride, u32 *work,
-                                          const u32 *order, u64 *steps, u64 *ni) {
+                                          const u32 *order, u32 mapn, const u32 *gbase,
+                                          u64 *steps, u64 *ni) {
     __shared__ u32 sh_src, sh_nt, sh_next;
     __shared__ u64 sh_red[WAVES_PER_WG];
-    C5Scratch C = c5_scratch(scratch + (u64)blockIdx.x * stride, n);
+    C5Scratch C = c5_scratch(scratch + (u64)blockIdx.x * stride, mapn);
     for (;;) {
         const u32 l = next_source(work, &sh_src, order, n);
         if (l >= n) break;
+        const u32 vb = gbase ? gbase[l] : 0;  // maps are indexed within l's graph
         const u32 bl = rp[l], dl = rp[l + 1] - bl;
         if (dl < 2) continue;
         const u64 kl = key[l];
         u64 nsteps = 0;  // loop iterations of this thread for this source
-        for (u32 i = threadIdx.x; i < dl; i += WG) C.mark[ci[bl + i]] = 1;
+        for (u32 i = threadIdx.x; i < dl; i += WG) C.mark[ci[bl + i] - vb] = 1;
         if (threadIdx.x == 0) { sh_nt = 0; sh_next = 0; }
         __syncthreads();
         // non-in-in wedges l - w - i, and 3-paths i <- j <- k -> l
@@ -852,13 +857,13 @@ __global__ void __launch_bounds__(WG) k_c5(const u32 *rp, const u32 *ci, const u
             const u32 w = ci[bl + iw];
             if (key[w] > kl) {  // l -> w, then w -> i
                 for (u64 q = out_ptr[w] + lane_id(); q < out_ptr[w + 1]; q += WAVE) {
-                    atomicAdd(&C.Wm[out_nbr[q]], 1u);
+                    atomicAdd(&C.Wm[out_nbr[q] - vb], 1u);
                     nsteps++;
                 }
             } else {  // w -> l, then any i ~ w
                 for (u32 s = rp[w] + lane_id(); s < rp[w + 1]; s += WAVE) {
                     const u32 i = ci[s];
-                    if (i != l) atomicAdd(&C.Wm[i], 1u);
+                    if (i != l) atomicAdd(&C.Wm[i - vb], 1u);
                     nsteps++;
                 }
                 // w plays k: 3-paths i <- j <- w -> l
@@ -866,15 +871,15 @@ __global__ void __launch_bounds__(WG) k_c5(const u32 *rp, const u32 *ci, const u
                 for (u64 qj = out_ptr[k]; qj < out_ptr[k + 1]; qj++) {
                     const u32 j = out_nbr[qj];
                     if (j == l) continue;
-                    const u64 jl = C.mark[j];
+                    const u64 jl = C.mark[j - vb];
                     for (u64 qi = out_ptr[j] + lane_id(); qi < out_ptr[j + 1]; qi += WAVE) {
                         const u32 i = out_nbr[qi];
                         nsteps++;
                         if (i == l) continue;
-                        u64 old = atomicAdd(&C.P[i], 1ull);
+                        u64 old = atomicAdd(&C.P[i - vb], 1ull);
                         if (old == 0) C.touched[atomicAdd(&sh_nt, 1u)] = i;
                         const u64 ik = out_adjacent(k, i, out_ptr, out_nbr) ? 1 : 0;
-                        atomic_add_u64(&C.CI[i], ik + jl);
+                        atomic_add_u64(&C.CI[i - vb], ik + jl);
                     }
                 }
             }
@@ -892,7 +897,7 @@ __global__ void __launch_bounds__(WG) k_c5(const u32 *rp, const u32 *ci, const u
                 const u64 tin = Tin[slw];
                 for (u64 q = out_ptr[w] + lane_id(); q < out_ptr[w + 1]; q += WAVE) {
                     const u32 i = out_nbr[q];
-                    const u64 p = C.P[i];
+                    const u64 p = C.P[i - vb];
                     if (p) accw += p - tin;  // w -> i holds; w -> l does not
                 }
             } else {  // w -> l
@@ -900,11 +905,11 @@ __global__ void __launch_bounds__(WG) k_c5(const u32 *rp, const u32 *ci, const u
                 for (u32 s = rp[w] + lane_id(); s < rp[w + 1]; s += WAVE) {
                     const u32 i = ci[s];
                     if (i == l) continue;
-                    const u64 p = C.P[i];
+                    const u64 p = C.P[i - vb];
                     if (!p) continue;
                     u64 corr = 0;
                     if (key[i] > kw) {  // w -> i
-                        const bool li = C.mark[i] && key[i] > kl;  // l -> i
+                        const bool li = C.mark[i - vb] && key[i] > kl;  // l -> i
                         corr = tin + (u64)Tmid[s] - (li ? 1 : 0);
                     }
                     accw += p - corr;
@@ -915,13 +920,13 @@ __global__ void __launch_bounds__(WG) k_c5(const u32 *rp, const u32 *ci, const u
                 for (u64 qj = out_ptr[k]; qj < out_ptr[k + 1]; qj++) {
                     const u32 j = out_nbr[qj];
                     if (j == l) continue;
-                    const u64 jl = C.mark[j];
+                    const u64 jl = C.mark[j - vb];
                     u64 accj = 0;
                     for (u64 qi = out_ptr[j] + lane_id(); qi < out_ptr[j + 1]; qi += WAVE) {
                         const u32 i = out_nbr[qi];
                         if (i == l) continue;
                         const u64 ik = out_adjacent(k, i, out_ptr, out_nbr) ? 1 : 0;
-                        accj += (u64)C.Wm[i] - ik - jl;
+                        accj += (u64)C.Wm[i - vb] - ik - jl;
                     }
                     accj = wave_sum_u64(accj);
                     if (lane_id() == 0) atomic_add_u64(&NI(j, 34), accj);
@@ -938,7 +943,7 @@ __global__ void __launch_bounds__(WG) k_c5(const u32 *rp, const u32 *ci, const u
         u64 accl = 0;
         for (u32 t = threadIdx.x; t < nt; t += WG) {
             const u32 i = C.touched[t];
-            const u64 v = C.P[i] * (u64)C.Wm[i] - C.CI[i];
+            const u64 v = C.P[i - vb] * (u64)C.Wm[i - vb] - C.CI[i - vb];
             accl += v;
             atomic_add_u64(&NI(i, 34), v);
         }
@@ -952,19 +957,19 @@ __global__ void __launch_bounds__(WG) k_c5(const u32 *rp, const u32 *ci, const u
         // reset: Wm was touched on every wedge endpoint, P/CI on 3-path ends
         for (u32 t = threadIdx.x; t < nt; t += WG) {
             const u32 i = C.touched[t];
-            C.P[i] = 0; C.CI[i] = 0;
+            C.P[i - vb] = 0; C.CI[i - vb] = 0;
         }
         if (threadIdx.x == 0) sh_next = 0;
         __syncthreads();
         wave_loop(&sh_next, dl, [&](u32 iw) {
             const u32 w = ci[bl + iw];
             if (key[w] > kl) {
-                for (u64 q = out_ptr[w] + lane_id(); q < out_ptr[w + 1]; q += WAVE) C.Wm[out_nbr[q]] = 0;
+                for (u64 q = out_ptr[w] + lane_id(); q < out_ptr[w + 1]; q += WAVE) C.Wm[out_nbr[q] - vb] = 0;
             } else {
-                for (u32 s = rp[w] + lane_id(); s < rp[w + 1]; s += WAVE) C.Wm[ci[s]] = 0;
+                for (u32 s = rp[w] + lane_id(); s < rp[w + 1]; s += WAVE) C.Wm[ci[s] - vb] = 0;
             }
         });
-        for (u32 i = threadIdx.x; i < dl; i += WG) C.mark[ci[bl + i]] = 0;
+        for (u32 i = threadIdx.x; i < dl; i += WG) C.mark[ci[bl + i] - vb] = 0;
         __syncthreads();
     }
 }

@@ -31,7 +31,7 @@ struct Buf {
 struct Layout {
     // phase 1
     Buf state, deg, src, rev, rnd, pdeg, front, key, outdeg, outptr, outnbr, outslot, tcnt,
-        triptr, bsum;
+        triptr, bsum, gbase;
     u64 p1_end = 0;
     // phase 2
     Buf tri_c, tri_sab, tri_sac, tri_sbc, T, Tin, Tmid, tllen, tlptr, tlcur, tl, E7, E9, C4e,
@@ -71,6 +71,7 @@ void layout_phase1(Layout &L, u32 n, u64 m) {
     place(c, L.triptr, 8ull * (m + 1));
     u64 maxlen = M2 + 1 > (u64)n + 1 ? M2 + 1 : (u64)n + 1;
     place(c, L.bsum, 8ull * (nblocks_scan(maxlen) + 1));
+    place(c, L.gbase, 4ull * n + 4);
     L.p1_end = c;
 }
 
@@ -84,8 +85,10 @@ u64 clique_stride(u32 dmax) {
     return align_up(4ull * dmax, 256) + 2 * 8ull * dmax * W + 2 * 8ull * dmax + 512;
 }
 
-void layout_phase2(Layout &L, u32 n, u64 m, u64 ntri, u32 dmax, int k_max, bool ni_in_out,
-                   u32 nwg_req) {
+// mapn: size of the per-source maps -- n, or the largest graph of a batch
+// (maps are then indexed by position within the source's graph).
+void layout_phase2(Layout &L, u32 n, u32 mapn, u64 m, u64 ntri, u32 dmax, int k_max,
+                   bool ni_in_out, u32 nwg_req) {
     const u64 M2 = 2 * m;
     u64 c = L.p1_end;
     place(c, L.tri_c, 4ull * (ntri + 1));
@@ -115,9 +118,9 @@ void layout_phase2(Layout &L, u32 n, u64 m, u64 ntri, u32 dmax, int k_max, bool 
     place(c, L.sbin, 4ull * n + 4);
     place(c, L.shist, 4ull * SCHED_BINS);
     place(c, L.order, 4ull * n + 4);
-    u64 stride = 8ull * n + 512;  // 4-cycle maps
+    u64 stride = 8ull * mapn + 512;  // 4-cycle maps (and the long-list sort)
     if (k_max >= 5) {
-        u64 ps = pair_stride(n);
+        u64 ps = pair_stride(mapn);
         if (ps > stride) stride = ps;
     }
     u64 cs = clique_stride(dmax);
@@ -145,6 +148,7 @@ int err_to_status(u32 e) {
     if (e & ERRB_DUP) return ORB_E_DUPLICATE;
     if (e & ERRB_ORDER) return ORB_E_NOT_SORTED;
     if (e & ERRB_ASYM) return ORB_E_ASYMMETRIC;
+    if (e & (ERRB_VPTR | ERRB_CROSS)) return ORB_E_BATCH;
     if (e & ERRB_INTERNAL) return ORB_E_INTERNAL;
     return ORB_OK;
 }
@@ -180,10 +184,10 @@ int zero_ranges(int which, u32 n, ZeroRange *r) {
     return 2;
 }
 
-int zero_scratch(int which, u32 n, unsigned char *scratch, const Layout &L, u32 nwg,
+int zero_scratch(int which, u32 mapn, unsigned char *scratch, const Layout &L, u32 nwg,
                  hipStream_t s) {
     ZeroRange r[2];
-    int k = zero_ranges(which, n, r);
+    int k = zero_ranges(which, mapn, r);
     for (int i = 0; i < k; i++)
         HCHK(hipMemset2DAsync(scratch + r[i].off, L.stride, 0, r[i].len, nwg, s));
     return ORB_OK;
@@ -254,8 +258,8 @@ int read_state(DevState *d, DevState *h, hipStream_t s) {
 
 // Phase 1: validation, peeling, orientation and triangle counting.  Leaves
 // ntri and the degeneracy in *hs.
-int run_phase1(const u32 *rp, const u32 *ci, u32 n, u64 m, void *ws, const Layout &L,
-               hipStream_t s, DevState *hs, Timer &tm) {
+int run_phase1(const u32 *rp, const u32 *ci, u32 n, u64 m, const u64 *vptr, u32 B, void *ws,
+               const Layout &L, hipStream_t s, DevState *hs, Timer &tm) {
     const u64 M2 = 2 * m;
     DevState *st = at<DevState>(ws, L.state);
     u32 *deg = at<u32>(ws, L.deg), *src = at<u32>(ws, L.src), *rev = at<u32>(ws, L.rev);
@@ -273,9 +277,18 @@ int run_phase1(const u32 *rp, const u32 *ci, u32 n, u64 m, void *ws, const Layou
     int rc = read_state(st, hs, s);
     if (rc) return rc;
     if (hs->err) return err_to_status(hs->err);
+    u32 *gbase = nullptr;
+    if (vptr) {
+        gbase = at<u32>(ws, L.gbase);
+        k_batch_index<<<grid_waves(B), WG, 0, s>>>(vptr, B, n, gbase, st);
+        HCHK(hipGetLastError());
+        rc = read_state(st, hs, s);
+        if (rc) return rc;
+        if (hs->err) return err_to_status(hs->err);
+    }
     if (n) {
         k_src_deg<<<grid_waves(n), WG, 0, s>>>(rp, n, src, deg);
-        k_rev<<<grid_for(M2, WG), WG, 0, s>>>(rp, ci, src, n, M2, rev, st);
+        k_rev<<<grid_for(M2, WG), WG, 0, s>>>(rp, ci, src, gbase, n, M2, rev, st);
         HCHK(hipGetLastError());
     }
     rc = read_state(st, hs, s);
@@ -319,7 +332,8 @@ int run_phase1(const u32 *rp, const u32 *ci, u32 n, u64 m, void *ws, const Layou
     return ORB_OK;
 }
 
-int count_impl(const u32 *rp, const u32 *ci, u32 n, u64 m, int k_max, u64 *counts, void *ws,
+int count_impl(const u32 *rp, const u32 *ci, u32 n, u64 m, const u64 *vptr, u32 B, int k_max,
+               u64 *counts, void *ws,
                u64 ws_bytes, u64 *ws_required, hipStream_t s, const orb_opts *opts,
                bool query_only) {
     const u32 flags = opts ? opts->flags : 0u;
@@ -340,12 +354,13 @@ int count_impl(const u32 *rp, const u32 *ci, u32 n, u64 m, int k_max, u64 *count
     Timer tm((flags & ORB_TIMING) && !query_only, s);
     DevState hs;
     memset(&hs, 0, sizeof hs);
-    int rc = run_phase1(rp, ci, n, m, ws, L, s, &hs, tm);
+    int rc = run_phase1(rp, ci, n, m, vptr, B, ws, L, s, &hs, tm);
     if (rc) return rc;
     const u64 ntri = hs.ntri;
     const u32 dmax = hs.maxlevel + 1;
     const bool ni_in_out = (K == ORB_NORB);
-    layout_phase2(L, n, m, ntri, dmax, k_max, ni_in_out, opts ? opts->num_wg : 0);
+    const u32 mapn = vptr ? (hs.gmax ? hs.gmax : 1) : n;
+    layout_phase2(L, n, mapn, m, ntri, dmax, k_max, ni_in_out, opts ? opts->num_wg : 0);
     if (ws_required) *ws_required = L.total;
     if (query_only) return ORB_OK;
     if (L.total > ws_bytes) return ORB_E_WORKSPACE;
@@ -371,6 +386,7 @@ int count_impl(const u32 *rp, const u32 *ci, u32 n, u64 m, int k_max, u64 *count
         *K4v = at<u64>(ws, L.K4v);
     u64 *ni = ni_in_out ? counts : at<u64>(ws, L.ni);
     unsigned char *scratch = at<unsigned char>(ws, L.scratch);
+    const u32 *gbase = vptr ? at<u32>(ws, L.gbase) : nullptr;
 
     // zero the accumulators (the contiguous phase-2 region up to ni) and
     // the per-source scratch
@@ -427,7 +443,7 @@ int count_impl(const u32 *rp, const u32 *ci, u32 n, u64 m, int k_max, u64 *count
             u32 *qlen = st->work + 15;
             k_tl_sort_small<<<grid_waves(M2), WG, 0, s>>>(src, ci, T, tlptr, tl, M2, tllen, qlen);
             k_tl_sort_wg<<<L.nwg, WG, 0, s>>>(rp, src, ci, T, tlptr, tl, tllen, qlen, scratch,
-                                              L.stride, n);
+                                              L.stride, mapn);
             HCHK(hipGetLastError());
         }
     }
@@ -437,11 +453,11 @@ int count_impl(const u32 *rp, const u32 *ci, u32 n, u64 m, int k_max, u64 *count
     u32 *work = st->work;
     int wi = 0;
     if (k_max >= 4) {
-        rc = zero_scratch(0, n, scratch, L, L.nwg, s);
+        rc = zero_scratch(0, mapn, scratch, L, L.nwg, s);
         if (rc) return rc;
         tm.mark("zero_c4");
         k_c4<<<L.nwg, WG, 0, s>>>(rp, ci, rev, key, n, scratch, L.stride, work + wi++, order,
-                                  C4v, C4e);
+                                  mapn, gbase, C4v, C4e);
         HCHK(hipGetLastError());
         tm.mark("c4");
         if (ntri) {
@@ -468,18 +484,18 @@ int count_impl(const u32 *rp, const u32 *ci, u32 n, u64 m, int k_max, u64 *count
             HCHK(hipGetLastError());
         }
         tm.mark("clique2_k4terms");
-        rc = zero_scratch(1, n, scratch, L, L.nwg, s);
+        rc = zero_scratch(1, mapn, scratch, L, L.nwg, s);
         if (rc) return rc;
         tm.mark("zero_pairs");
         k_pairs<<<L.nwg, WG, 0, s>>>(rp, ci, src, rev, deg, T, tlptr, tl, n, scratch, L.stride,
-                                     work + wi++, order, steps_out, Q, ni);
+                                     work + wi++, order, mapn, gbase, steps_out, Q, ni);
         HCHK(hipGetLastError());
         tm.mark("pairs");
-        rc = zero_scratch(2, n, scratch, L, L.nwg < 256 ? L.nwg : 256, s);
+        rc = zero_scratch(2, mapn, scratch, L, L.nwg < 256 ? L.nwg : 256, s);
         if (rc) return rc;
         tm.mark("zero_c5");
         k_c5<<<L.nwg < 256 ? L.nwg : 256, WG, 0, s>>>(rp, ci, key, outptr, outnbr, outslot, Tin, Tmid, n, scratch,
-                                  L.stride, work + wi++, order, steps_out, ni);
+                                  L.stride, work + wi++, order, mapn, gbase, steps_out, ni);
         HCHK(hipGetLastError());
         tm.mark("c5");
     }
@@ -520,7 +536,7 @@ int orbit_num_orbits(int k_max) {
 int orbit_count_ex(const uint32_t *row_ptr, const uint32_t *col_idx, uint32_t n, uint64_t m,
                    int k_max, uint64_t *counts, void *workspace, uint64_t ws_bytes,
                    uint64_t *ws_required, void *stream, const orb_opts *opts) {
-    return count_impl(row_ptr, col_idx, n, m, k_max, (u64 *)counts, workspace, ws_bytes,
+    return count_impl(row_ptr, col_idx, n, m, nullptr, 0, k_max, (u64 *)counts, workspace, ws_bytes,
                       (u64 *)ws_required, (hipStream_t)stream, opts, false);
 }
 
@@ -534,7 +550,7 @@ int orbit_workspace_query(const uint32_t *row_ptr, const uint32_t *col_idx, uint
     void *tmp = nullptr;
     if (hipMalloc(&tmp, L.p1_end) != hipSuccess) return ORB_E_DEVICE;
     u64 req = 0;
-    int rc = count_impl(row_ptr, col_idx, n, m, k_max, nullptr, tmp, L.p1_end, &req,
+    int rc = count_impl(row_ptr, col_idx, n, m, nullptr, 0, k_max, nullptr, tmp, L.p1_end, &req,
                         (hipStream_t)stream, opts, true);
     (void)hipFree(tmp);
     if (rc) return rc;
@@ -553,6 +569,83 @@ int orbit_count(const uint32_t *row_ptr, const uint32_t *col_idx, uint32_t n, ui
                         nullptr);
     (void)hipFree(ws);
     return rc;
+}
+
+int orbit_count_batched(const uint64_t *vptr, uint32_t num_graphs, const uint32_t *row_ptr,
+                        const uint32_t *col_idx, uint32_t n, uint64_t m, int k_max,
+                        uint64_t *counts, void *workspace, uint64_t ws_bytes,
+                        uint64_t *ws_required, void *stream, const orb_opts *opts) {
+    if (!vptr) return ORB_E_INVALID_ARG;
+    return count_impl(row_ptr, col_idx, n, m, (const u64 *)vptr, num_graphs, k_max,
+                      (u64 *)counts, workspace, ws_bytes, (u64 *)ws_required,
+                      (hipStream_t)stream, opts, false);
+}
+
+int orbit_workspace_query_batched(const uint64_t *vptr, uint32_t num_graphs,
+                                  const uint32_t *row_ptr, const uint32_t *col_idx, uint32_t n,
+                                  uint64_t m, int k_max, void *stream, const orb_opts *opts,
+                                  uint64_t *bytes) {
+    if (!bytes || !vptr || !orbit_num_orbits(k_max)) return ORB_E_INVALID_ARG;
+    if (2 * m >= (1ull << 32)) return ORB_E_INVALID_ARG;
+    Layout L;
+    layout_phase1(L, n, m);
+    void *tmp = nullptr;
+    if (hipMalloc(&tmp, L.p1_end) != hipSuccess) return ORB_E_DEVICE;
+    u64 req = 0;
+    int rc = count_impl(row_ptr, col_idx, n, m, (const u64 *)vptr, num_graphs, k_max, nullptr,
+                        tmp, L.p1_end, &req, (hipStream_t)stream, opts, true);
+    (void)hipFree(tmp);
+    if (rc) return rc;
+    *bytes = req;
+    return ORB_OK;
+}
+
+int orbit_autotune(const uint64_t *vptr, uint32_t num_graphs, const uint32_t *row_ptr,
+                   const uint32_t *col_idx, uint32_t n, uint64_t m, int k_max, uint64_t *counts,
+                   void *workspace, uint64_t ws_bytes, void *stream, const orb_opts *base,
+                   const uint32_t *nwg_candidates, int num_candidates, orb_opts *best,
+                   float *best_ms) {
+    if (!best || !nwg_candidates || num_candidates <= 0) return ORB_E_INVALID_ARG;
+    orb_opts o;
+    memset(&o, 0, sizeof o);
+    if (base) o = *base;
+    const u32 keep_flags = o.flags & ~ORB_TIMING;
+    const u32 nsched = o.mlp_weights ? 3 : 2;
+    hipStream_t s = (hipStream_t)stream;
+    auto run = [&](const orb_opts &x, float *ms) -> int {
+        int rc = count_impl(row_ptr, col_idx, n, m, (const u64 *)vptr, num_graphs, k_max,
+                            (u64 *)counts, workspace, ws_bytes, nullptr, s, &x, false);
+        if (rc) return rc;
+        float t = 0;
+        for (int i = 0; i < g_nphase; i++) t += g_phase_ms[i];
+        *ms = t;
+        return ORB_OK;
+    };
+    float bms = -1, ms = 0;
+    orb_opts b = o;
+    bool warm = false;
+    for (int c = 0; c < num_candidates; c++) {
+        for (u32 sc = 0; sc < nsched; sc++) {
+            orb_opts x = o;
+            x.flags = keep_flags | ORB_TIMING;
+            x.num_wg = nwg_candidates[c];
+            x.schedule = sc;
+            int rc = run(x, &ms);
+            if (rc == ORB_E_WORKSPACE) break;  // this candidate does not fit
+            if (rc) return rc;
+            if (!warm) {  // the first run also loads the code and warms caches
+                warm = true;
+                rc = run(x, &ms);
+                if (rc) return rc;
+            }
+            if (bms < 0 || ms < bms) { bms = ms; b = x; }
+        }
+    }
+    if (bms < 0) return ORB_E_WORKSPACE;
+    b.flags = keep_flags;
+    *best = b;
+    if (best_ms) *best_ms = bms;
+    return ORB_OK;
 }
 
 int orbit_mlp_init(float *weights, uint32_t seed, void *stream) {
@@ -613,6 +706,7 @@ const char *orbit_strerror(int status) {
         case ORB_E_WORKSPACE: return "workspace too small";
         case ORB_E_DEVICE: return "HIP call failed";
         case ORB_E_INTERNAL: return "internal consistency check failed";
+        case ORB_E_BATCH: return "batched input: bad graph offsets or an edge joining two graphs";
         default: return "unknown status";
     }
 }

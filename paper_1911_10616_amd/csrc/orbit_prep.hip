@@ -22,13 +22,14 @@ __global__ void k_src_deg(const u32 *rp, u32 n, u32 *src, u32 *deg) {
 // Per slot s = (u,v): range, self-loop, order and duplicate checks, and the
 // reverse slot rev[s] = position of u in N(v) (found by binary search; its
 // absence means the CSR is not symmetric).
-__global__ void k_rev(const u32 *rp, const u32 *ci, const u32 *src, u32 n, u64 M2, u32 *rev,
-                      DevState *st) {
+__global__ void k_rev(const u32 *rp, const u32 *ci, const u32 *src, const u32 *gbase, u32 n,
+                      u64 M2, u32 *rev, DevState *st) {
     for (u64 s = GTID; s < M2; s += GSTRIDE) {
         u32 u = src[s], v = ci[s];
         rev[s] = (u32)s;
         if (v >= n) { atomicOr(&st->err, ERRB_RANGE); continue; }
         if (v == u) atomicOr(&st->err, ERRB_LOOP);
+        if (gbase && gbase[u] != gbase[v]) atomicOr(&st->err, ERRB_CROSS);
         if (s + 1 < rp[u + 1]) {
             u32 w = ci[s + 1];
             if (w == v) atomicOr(&st->err, ERRB_DUP);
@@ -38,6 +39,22 @@ __global__ void k_rev(const u32 *rp, const u32 *ci, const u32 *src, u32 n, u64 M
         u32 i = bfind(ci + b, len, u);
         if (i == UNSET) atomicOr(&st->err, ERRB_ASYM);
         else rev[s] = b + i;
+    }
+}
+
+// Batched input: graph g owns vertices [vptr[g], vptr[g+1]).  Checks that
+// the offsets start at 0, never decrease and end at n; records each
+// vertex's first vertex gbase[v] and the largest graph.  One wave per graph.
+__global__ void k_batch_index(const u64 *vptr, u32 B, u32 n, u32 *gbase, DevState *st) {
+    if (GTID == 0 && (vptr[0] != 0 || vptr[B] != n)) atomicOr(&st->err, ERRB_VPTR);
+    for (u64 g = GWAVE; g < B; g += NWAVES) {
+        const u64 lo = vptr[g], hi = vptr[g + 1];
+        if (hi < lo || hi > n) {
+            if (lane_id() == 0) atomicOr(&st->err, ERRB_VPTR);
+            continue;
+        }
+        for (u64 v = lo + lane_id(); v < hi; v += WAVE) gbase[v] = (u32)lo;
+        if (lane_id() == 0) atomicMax(&st->gmax, (u32)(hi - lo));
     }
 }
 

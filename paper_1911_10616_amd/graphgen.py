@@ -19,7 +19,7 @@ import numpy as np
 __all__ = [
     "csr_from_edges", "erdos_renyi", "chung_lu", "rmat", "barabasi_albert",
     "complete", "cycle", "star", "complete_bipartite", "path", "from_edge_list",
-    "random_small", "relabel", "CONFIG_SEED_BASE", "workload",
+    "random_small", "relabel", "batch_small", "CONFIG_SEED_BASE", "workload",
 ]
 
 CONFIG_SEED_BASE = 0x5EED0000
@@ -195,6 +195,69 @@ def relabel(row_ptr, col_idx, seed: int):
     return csr_from_edges(n, perm[src[keep]], perm[col_idx[keep].astype(np.int64)])
 
 
+def batch_small(num_graphs: int, seed: int, nmin: int = 10, nmax: int = 500,
+                er_mean_deg: float = 6.0, ba_m: int = 3):
+    """Many small graphs as one CSR (the disjoint union over global ids).
+
+    Graph g has n_g ~ uniform{nmin..nmax} vertices; even g are
+    Erdos-Renyi G(n_g, er_mean_deg / (n_g - 1)), odd g Barabasi-Albert with
+    ba_m edges per new vertex (the model of ``barabasi_albert``: a star on
+    ba_m + 1 vertices, then each new vertex draws endpoints of existing
+    edges until it has ba_m distinct targets).  Returns (vptr, row_ptr,
+    col_idx): graph g owns vertices vptr[g] .. vptr[g+1]-1.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sizes = rng.integers(nmin, nmax + 1, num_graphs).astype(np.int64)
+    vptr = np.zeros(num_graphs + 1, dtype=np.int64)
+    np.cumsum(sizes, out=vptr[1:])
+    us, vs = [], []
+    # Erdos-Renyi graphs: a binomial number of distinct pairs
+    for g in range(0, num_graphs, 2):
+        n = int(sizes[g])
+        pairs = n * (n - 1) // 2
+        k = int(rng.binomial(pairs, min(1.0, er_mean_deg / (n - 1))))
+        idx = rng.choice(pairs, size=k, replace=False)
+        # pair index -> (i, j), i < j, row-major over the upper triangle
+        i = (n - 2 - np.floor(np.sqrt(-8.0 * idx + 4.0 * n * (n - 1) - 7) / 2.0 - 0.5)).astype(np.int64)
+        j = idx + i + 1 - (n * (n - 1) // 2 - (n - i) * (n - i - 1) // 2)
+        us.append(vptr[g] + i)
+        vs.append(vptr[g] + j)
+    # Barabasi-Albert graphs, grown in lockstep (one new vertex per graph per step)
+    ba = np.arange(1, num_graphs, 2)
+    if ba.size:
+        m0 = ba_m + 1
+        nb = sizes[ba]
+        cap = 2 * (ba_m + ba_m * max(0, int(nb.max()) - m0))
+        ends = np.zeros((ba.size, cap), dtype=np.int64)  # local ids of edge endpoints
+        ends[:, 0:2 * ba_m:2] = 0
+        ends[:, 1:2 * ba_m:2] = np.arange(1, m0)
+        length = np.full(ba.size, 2 * ba_m, dtype=np.int64)
+        us.append(np.repeat(vptr[ba], ba_m))
+        vs.append((vptr[ba][:, None] + np.arange(1, m0)[None, :]).ravel())
+        for new in range(m0, int(nb.max())):
+            act = np.flatnonzero(nb > new)
+            chosen = np.full((act.size, ba_m), -1, dtype=np.int64)
+            for k in range(ba_m):
+                todo = np.arange(act.size)
+                while todo.size:
+                    pick = ends[act[todo], (rng.random(todo.size) * length[act[todo]]).astype(np.int64)]
+                    dup = (chosen[todo, :k] == pick[:, None]).any(axis=1)
+                    chosen[todo[~dup], k] = pick[~dup]
+                    todo = todo[dup]
+            base = vptr[ba[act]]
+            us.append(np.repeat(base + new, ba_m))
+            vs.append((base[:, None] + chosen).ravel())
+            rows = act
+            pos = length[rows]
+            ends[rows[:, None], pos[:, None] + 2 * np.arange(ba_m)[None, :]] = new
+            ends[rows[:, None], pos[:, None] + 2 * np.arange(ba_m)[None, :] + 1] = chosen
+            length[rows] += 2 * ba_m
+    u = np.concatenate(us) if us else np.zeros(0, np.int64)
+    v = np.concatenate(vs) if vs else np.zeros(0, np.int64)
+    rp, ci = csr_from_edges(int(vptr[-1]), u, v)
+    return vptr.astype(np.uint64), rp, ci
+
+
 def workload(name: str):
     """The five named synthetic workloads (seed = 0x5EED0000 + index)."""
     if name == "er2000":
@@ -205,6 +268,8 @@ def workload(name: str):
         return relabel(*workload("chunglu1m"), CONFIG_SEED_BASE + 6)
     if name == "chunglu250k":  # a smaller graph of the same family (cost-model training)
         return chung_lu(250_000, 20.0, 2.1, 12_500.0, 2_500_000, CONFIG_SEED_BASE + 7)
+    if name == "batch100k":
+        return batch_small(100_000, CONFIG_SEED_BASE + 4)
     if name == "rmat22":
         return rmat(22, 16, seed=CONFIG_SEED_BASE + 3)
     if name == "rmat24":

@@ -22,7 +22,8 @@ MLP_PARAMS = 1217
 
 EXPORTS = ("orbit_num_orbits", "orbit_count", "orbit_workspace_query", "orbit_count_ex",
            "orbit_strerror", "orbit_last_phase_times", "orbit_last_stats", "orbit_mlp_init",
-           "orbit_mlp_predict", "orbit_mlp_grad", "orbit_mlp_train")
+           "orbit_mlp_predict", "orbit_mlp_grad", "orbit_mlp_train", "orbit_count_batched",
+           "orbit_workspace_query_batched", "orbit_autotune")
 
 
 class OrbError(RuntimeError):
@@ -70,6 +71,17 @@ def _load():
     lib.orbit_mlp_train.argtypes = [vp, vp, ctypes.c_uint32, vp, vp, ctypes.c_uint32,
                                     ctypes.c_uint32, ctypes.c_float, ctypes.c_uint32, vp]
     lib.orbit_mlp_train.restype = ctypes.c_int
+    u32 = ctypes.c_uint32
+    lib.orbit_count_batched.argtypes = [vp, u32, vp, vp, u32, u64, ctypes.c_int, vp, vp, u64,
+                                        ctypes.POINTER(u64), vp, ctypes.POINTER(_Opts)]
+    lib.orbit_count_batched.restype = ctypes.c_int
+    lib.orbit_workspace_query_batched.argtypes = [vp, u32, vp, vp, u32, u64, ctypes.c_int, vp,
+                                                  ctypes.POINTER(_Opts), ctypes.POINTER(u64)]
+    lib.orbit_workspace_query_batched.restype = ctypes.c_int
+    lib.orbit_autotune.argtypes = [vp, u32, vp, vp, u32, u64, ctypes.c_int, vp, vp, u64, vp,
+                                   ctypes.POINTER(_Opts), ctypes.POINTER(u32), ctypes.c_int,
+                                   ctypes.POINTER(_Opts), ctypes.POINTER(ctypes.c_float)]
+    lib.orbit_autotune.restype = ctypes.c_int
     return lib
 
 
@@ -205,6 +217,88 @@ def last_stats():
     k = _lib.orbit_last_stats(v, 6)
     keys = ("n", "m", "triangles", "degeneracy", "wedges", "diamonds")
     return {keys[i]: int(v[i]) for i in range(k)}
+
+
+def _dev_u64(a, device="cuda"):
+    import torch
+    if isinstance(a, torch.Tensor):
+        return a.to(device).contiguous()
+    return torch.as_tensor(np.asarray(a, dtype=np.uint64).view(np.int64)).to(device).contiguous()
+
+
+class BatchCounter:
+    """Counts orbits of many small graphs in one call (orbit_count_batched).
+
+    vptr: uint64[B+1] graph offsets; row_ptr/col_idx: the CSR of the
+    disjoint union over global ids.  Rows vptr[g]..vptr[g+1]-1 of the
+    result are graph g's counts.  Options as for Counter."""
+
+    def __init__(self, vptr, row_ptr, col_idx, k_max=5, noninduced=False, num_wg=0,
+                 stream=None, schedule="id", mlp_weights=None):
+        import torch
+        self.vptr = _dev_u64(vptr)
+        self.B = self.vptr.numel() - 1
+        self.rp, self.ci = _dev_csr(row_ptr, col_idx)
+        self.n = self.rp.numel() - 1
+        self.m = int(self.rp[-1].item()) // 2
+        self.k_max = k_max
+        self.K = num_orbits(k_max)
+        self.stream = stream
+        self.noninduced = noninduced
+        self._w = mlp_weights
+        self.set_options(num_wg, schedule)
+        self.out = torch.empty((max(self.n, 1), self.K), dtype=torch.int64, device=self.rp.device)
+
+    def _args(self):
+        return (ctypes.c_void_p(self.vptr.data_ptr()), self.B, ctypes.c_void_p(self.rp.data_ptr()),
+                ctypes.c_void_p(self.ci.data_ptr()), self.n, self.m, self.k_max)
+
+    def set_options(self, num_wg, schedule):
+        """(Re)size the workspace for these options."""
+        import torch
+        sched = SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule)
+        self.opts = _opts(self.noninduced, False, num_wg, sched, self._w)
+        self.topts = _opts(self.noninduced, True, num_wg, sched, self._w)
+        need = ctypes.c_uint64(0)
+        _check(_lib.orbit_workspace_query_batched(*self._args(), _stream_ptr(self.stream),
+                                                  ctypes.byref(self.opts), ctypes.byref(need)),
+               "orbit_workspace_query_batched")
+        self.ws_bytes = int(need.value)
+        self.ws = torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8, device=self.rp.device)
+
+    def run(self, timing=False):
+        need = ctypes.c_uint64(0)
+        o = self.topts if timing else self.opts
+        _check(_lib.orbit_count_batched(*self._args(), ctypes.c_void_p(self.out.data_ptr()),
+                                        ctypes.c_void_p(self.ws.data_ptr()), self.ws_bytes,
+                                        ctypes.byref(need), _stream_ptr(self.stream),
+                                        ctypes.byref(o)), "orbit_count_batched")
+        return self.out[: self.n]
+
+    def autotune(self, nwg_candidates=(256, 512, 1024, 2048, 4096)):
+        """Pick num_wg and schedule by timing each candidate (orbit_autotune);
+        keeps the choice and returns (num_wg, schedule, gpu_ms)."""
+        import torch
+        big = max(nwg_candidates)
+        self.set_options(big, self.opts.schedule)
+        cand = (ctypes.c_uint32 * len(nwg_candidates))(*nwg_candidates)
+        best = _Opts()
+        ms = ctypes.c_float(0)
+        base = _opts(self.noninduced, False, 0, SCHED_ID, self._w)
+        _check(_lib.orbit_autotune(*self._args(), ctypes.c_void_p(self.out.data_ptr()),
+                                   ctypes.c_void_p(self.ws.data_ptr()), self.ws_bytes,
+                                   _stream_ptr(self.stream), ctypes.byref(base), cand,
+                                   len(nwg_candidates), ctypes.byref(best), ctypes.byref(ms)),
+               "orbit_autotune")
+        self.set_options(best.num_wg, best.schedule)
+        return int(best.num_wg), int(best.schedule), float(ms.value)
+
+
+def count_batched(vptr, row_ptr, col_idx, k_max=5, noninduced=False, num_wg=0,
+                  schedule="id") -> np.ndarray:
+    """uint64[n, K]: per-graph counts of a batch, concatenated by graph."""
+    c = BatchCounter(vptr, row_ptr, col_idx, k_max, noninduced, num_wg, schedule=schedule)
+    return c.run().cpu().numpy().view(np.uint64)
 
 
 def _check(st, where):

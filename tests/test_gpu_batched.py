@@ -1,0 +1,135 @@
+"""Batched mode: many small graphs in one call, on the GPU through the C ABI.
+
+Bit-exact against the oracle graph by graph, and against the single-graph
+path on the disjoint union (the same integers, since every orbit lies in
+one connected component).
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1911_10616_amd import graphgen as gg
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def orbit():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1911_10616_amd import orbit as o
+    return o
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _graph(vptr, rp, ci, g):
+    a, b = int(vptr[g]), int(vptr[g + 1])
+    return (rp[a:b + 1] - rp[a]).astype(np.uint32), (ci[rp[a]:rp[b]] - a).astype(np.uint32)
+
+
+@pytest.mark.parametrize("schedule", ["id", "static"])
+def test_small_batch_per_graph_oracle(orbit, schedule):
+    vptr, rp, ci = gg.batch_small(60, 101, nmin=5, nmax=40)
+    _say("batch of 60, n", len(rp) - 1, "schedule", schedule)
+    got = orbit.count_batched(vptr, rp, ci, 5, schedule=schedule)
+    for g in range(60):
+        a, b = int(vptr[g]), int(vptr[g + 1])
+        np.testing.assert_array_equal(got[a:b], oracle.induced_counts(*_graph(vptr, rp, ci, g)),
+                                      err_msg=f"graph {g}")
+
+
+@pytest.mark.parametrize("k_max", [3, 4])
+def test_batch_smaller_kmax(orbit, k_max):
+    vptr, rp, ci = gg.batch_small(30, 102, nmin=5, nmax=30)
+    got = orbit.count_batched(vptr, rp, ci, k_max)
+    K = orbit.num_orbits(k_max)
+    for g in range(30):
+        a, b = int(vptr[g]), int(vptr[g + 1])
+        ref = oracle.induced_counts(*_graph(vptr, rp, ci, g), kmax=k_max)[:, :K]
+        np.testing.assert_array_equal(got[a:b], ref, err_msg=f"graph {g}")
+
+
+def test_noninduced_batch(orbit):
+    vptr, rp, ci = gg.batch_small(20, 103, nmin=5, nmax=20)
+    got = orbit.count_batched(vptr, rp, ci, 5, noninduced=True)
+    for g in range(20):
+        a, b = int(vptr[g]), int(vptr[g + 1])
+        np.testing.assert_array_equal(got[a:b], oracle.noninduced_counts(*_graph(vptr, rp, ci, g)))
+
+
+def test_batch_equals_union_and_oracle_sample(orbit):
+    vptr, rp, ci = gg.batch_small(1000, 104)
+    _say("batch of 1000, n", len(rp) - 1, "m", ci.size // 2)
+    got = orbit.count_batched(vptr, rp, ci, 5)
+    union = orbit.count(rp, ci, 5)
+    np.testing.assert_array_equal(got, union)
+    for g in (0, 1, 2, 3, 998, 999):
+        a, b = int(vptr[g]), int(vptr[g + 1])
+        np.testing.assert_array_equal(got[a:b], oracle.induced_counts(*_graph(vptr, rp, ci, g),
+                                                                     threads=8))
+
+
+def test_batch_with_empty_and_single_vertex_graphs(orbit):
+    parts = [gg.complete(5), gg.csr_from_edges(1, [], []), gg.cycle(6), gg.star(4)]
+    sizes = [0, 5, 0, 1, 6, 0, 5]
+    order = [None, 0, None, 1, 2, None, 3]
+    vptr = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
+    us, vs = [], []
+    for off, p in zip(vptr[:-1], order):
+        if p is None:
+            continue
+        r, c = parts[p]
+        src = np.repeat(np.arange(len(r) - 1), np.diff(r))
+        us.append(src + int(off))
+        vs.append(c.astype(np.int64) + int(off))
+    rp, ci = gg.csr_from_edges(int(vptr[-1]), np.concatenate(us), np.concatenate(vs))
+    got = orbit.count_batched(vptr, rp, ci, 5)
+    for g in range(len(sizes)):
+        a, b = int(vptr[g]), int(vptr[g + 1])
+        if a == b:
+            continue
+        np.testing.assert_array_equal(got[a:b], oracle.induced_counts(*_graph(vptr, rp, ci, g)))
+
+
+def test_batched_input_errors(orbit):
+    import torch
+    vptr, rp, ci = gg.batch_small(8, 105, nmin=5, nmax=12)
+    n = len(rp) - 1
+    def status(v, r, c):
+        vd = torch.from_numpy(np.asarray(v, np.uint64).view(np.int64)).cuda()
+        rd = torch.from_numpy(np.asarray(r, np.uint32).view(np.int32)).cuda()
+        cd = torch.from_numpy(np.asarray(c, np.uint32).view(np.int32)).cuda()
+        need = ctypes.c_uint64(0)
+        o = orbit._Opts(0, 0, 0, 0, None, None, None)
+        return orbit._lib.orbit_workspace_query_batched(
+            ctypes.c_void_p(vd.data_ptr()), len(v) - 1, ctypes.c_void_p(rd.data_ptr()),
+            ctypes.c_void_p(cd.data_ptr()), len(r) - 1, int(r[-1]) // 2, 5, None,
+            ctypes.byref(o), ctypes.byref(need))
+    assert status(vptr, rp, ci) == 0
+    bad = vptr.copy(); bad[3] = bad[2] - np.uint64(1)
+    assert status(bad, rp, ci) == -10          # decreasing offsets
+    bad = vptr.copy(); bad[-1] -= np.uint64(1)
+    assert status(bad, rp, ci) == -10          # does not end at n
+    bad = vptr.copy(); bad[0] = np.uint64(1)
+    assert status(bad, rp, ci) == -10          # does not start at 0
+    src = np.repeat(np.arange(n), np.diff(rp))
+    keep = src < ci
+    rp2, ci2 = gg.csr_from_edges(n, np.concatenate([src[keep], [0]]),
+                                 np.concatenate([ci[keep].astype(np.int64), [n - 1]]))
+    assert status(vptr, rp2, ci2) == -10       # an edge between two graphs
+
+
+def test_autotune_keeps_counts(orbit):
+    vptr, rp, ci = gg.batch_small(400, 106)
+    c = orbit.BatchCounter(vptr, rp, ci, 5)
+    ref = c.run().cpu().numpy().copy()
+    nwg, sched, ms = c.autotune((128, 512, 2048))
+    _say("autotune", nwg, sched, ms)
+    assert nwg in (128, 512, 2048) and sched in (0, 1) and ms > 0
+    np.testing.assert_array_equal(c.run().cpu().numpy(), ref)
