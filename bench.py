@@ -114,8 +114,12 @@ def run_batched(args, orbit, gg, rank):
     vptr, rp, ci = gg.workload(args.workload)
     n = len(rp) - 1
     m = ci.size // 2
-    bc = orbit.BatchCounter(vptr, rp, ci, k_max=5)
-    nwg, sched, tune_ms = bc.autotune((256, 512, 1024, 2048, 4096))
+    if args.no_autotune:
+        nwg, sched, groups, tune_ms = 1024, 0, 2, 0.0
+        bc = orbit.BatchCounter(vptr, rp, ci, k_max=5, num_wg=nwg, groups="wave")
+    else:
+        bc = orbit.BatchCounter(vptr, rp, ci, k_max=5)
+        nwg, sched, groups, tune_ms = bc.autotune((512, 1024, 2048, 4096))
     for _ in range(args.warmup):
         bc.run(timing=True)
     torch.cuda.synchronize()
@@ -131,6 +135,18 @@ def run_batched(args, orbit, gg, rank):
     ms_step = 1000.0 * el / args.steps
     phases = {k: v / args.steps for k, v in phases.items()}
     got = bc.out[:n].clone()
+    # the same count captured as one HIP graph and replayed
+    plan = orbit.Plan(bc)
+    plan.launch()
+    plan.status()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.launch()
+    plan.status()
+    graph_ms = 1000.0 * (time.perf_counter() - t2) / args.steps
+    graph_same = bool(torch.equal(bc.out[:n], got))
+    plan.close()
     del bc
     torch.cuda.empty_cache()
     compare = None
@@ -165,11 +181,13 @@ def run_batched(args, orbit, gg, rank):
                    "m": m, "k_max": 5, "orbits": 73,
                    "output": "induced uint64 counts n x 73, concatenated per graph",
                    "autotuned": {"num_wg": nwg, "schedule": ["id", "static", "mlp"][sched],
+                                 "groups": ["auto", "workgroup", "wave"][groups],
                                  "gpu_ms": round(tune_ms, 3)}},
         "phases_ms": {k: round(v, 3) for k, v in phases.items()},
         "dominant_phase": dom,
         "work": stats,
     }
+    line["graph_replay"] = {"ms_per_step": round(graph_ms, 3), "identical_counts": graph_same}
     if compare is not None:
         line["vs_plain_path"] = compare
     if rank == 0:
@@ -184,6 +202,8 @@ def main():
     ap.add_argument("--workload", default="chunglu1m", choices=sorted(WORKLOADS))
     ap.add_argument("--schedule", default="mlp", choices=("id", "static", "mlp"),
                     help="order of sources in the per-source kernels")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="batched workload: 1024 workgroups, id schedule, no tuning runs")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the one-step run with the static schedule")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)

@@ -79,6 +79,14 @@ extern "C" {
 #define ORB_SCHED_MLP 2u    /* heaviest first by the cost model's prediction
                                (bins of 4 * predicted log2 steps) */
 
+/* execution groups of the per-source kernels (counts are the same either way) */
+#define ORB_GROUPS_AUTO 0u  /* waves when every source is light: per-source maps of
+                               <= 4096 entries (graphs, or a batch's largest graph, of
+                               <= 4096 vertices) and degeneracy < 64 */
+#define ORB_GROUPS_WG 1u    /* a 256-thread workgroup per source */
+#define ORB_GROUPS_WAVE 2u  /* a 64-lane wave per source, four sources per workgroup,
+                               queue entries taken 16 at a time */
+
 /* cost model: a 3 -> 32 -> 32 -> 1 fp32 ReLU network, parameters packed as
  * W1[32][3], b1[32], W2[32][32], b2[32], W3[32], b3 */
 #define ORB_MLP_PARAMS 1217
@@ -87,7 +95,8 @@ typedef struct orb_opts {
     uint32_t flags;           /* ORB_* option bits */
     uint32_t num_wg;          /* persistent workgroups for the per-source kernels; 0 = default */
     uint32_t schedule;        /* ORB_SCHED_* */
-    uint32_t reserved;        /* must be 0 */
+    uint32_t groups;          /* ORB_GROUPS_*: who works on one source in the per-source
+                                 kernels */
     const float *mlp_weights; /* device, ORB_MLP_PARAMS floats; needed by ORB_SCHED_MLP */
     float *features_out;      /* device, n*3 floats, nullable: per-vertex cost features
                                  (log2(1+d+(u)), log2(1+sum_{w in N+(u)} d+(w)), log2(1+d(u)))
@@ -143,16 +152,38 @@ int orbit_workspace_query_batched(const uint64_t *vptr, uint32_t num_graphs,
                                   uint64_t *bytes);
 
 /* Autotuner: runs the count (batched when vptr is not NULL, else one graph)
- * once per candidate workgroup count and schedule (id, static thresholds,
- * and the cost model when base->mlp_weights is set), timed with HIP events,
- * and returns in *best the options (base's flags, the fastest num_wg and
- * schedule) and in *best_ms its GPU time.  Candidates whose workspace does
+ * once per candidate workgroup count, execution group (workgroup or wave
+ * per source) and schedule (id, static thresholds, and the cost model when
+ * base->mlp_weights is set), timed with HIP events, and returns in *best
+ * the options (base's flags, the fastest num_wg, groups and schedule) and
+ * in *best_ms its GPU time.  Candidates whose workspace does
  * not fit ws_bytes are skipped.  counts receives the last run's counts. */
 int orbit_autotune(const uint64_t *vptr, uint32_t num_graphs, const uint32_t *row_ptr,
                    const uint32_t *col_idx, uint32_t n, uint64_t m, int k_max, uint64_t *counts,
                    void *workspace, uint64_t ws_bytes, void *stream, const orb_opts *base,
                    const uint32_t *nwg_candidates, int num_candidates, orb_opts *best,
                    float *best_ms);
+
+/* ---- plans: the whole count captured as one HIP graph.
+ * orbit_plan_create runs the count once (validating the input and fixing
+ * every data-dependent choice: peel launches, triangle count, degeneracy,
+ * largest graph), then captures the same kernel sequence -- with nothing
+ * read back to the host -- into a graph bound to these buffers.
+ * orbit_plan_launch replays it on `stream` (asynchronous, no host sync): it
+ * recounts the buffers it was built on, so the input must be unchanged
+ * (the graph ends with a check that the sizes agree and records
+ * ORB_E_INTERNAL otherwise; a changed input is not otherwise guarded).
+ * orbit_plan_status waits for `stream` and returns the status of the last
+ * replay.  vptr may be NULL (one graph).  ORB_TIMING, features_out and
+ * steps_out are ignored.  The workspace must outlive the plan. */
+typedef struct orb_plan orb_plan;
+int orbit_plan_create(const uint64_t *vptr, uint32_t num_graphs, const uint32_t *row_ptr,
+                      const uint32_t *col_idx, uint32_t n, uint64_t m, int k_max,
+                      uint64_t *counts, void *workspace, uint64_t ws_bytes, void *stream,
+                      const orb_opts *opts, orb_plan **plan);
+int orbit_plan_launch(orb_plan *plan, void *stream);
+int orbit_plan_status(orb_plan *plan, void *stream);
+int orbit_plan_destroy(orb_plan *plan);
 
 /* Human-readable text of a status code (static storage). */
 const char *orbit_strerror(int status);

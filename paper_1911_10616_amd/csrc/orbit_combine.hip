@@ -6,19 +6,37 @@
 
 #define NI(u, o) ni[(u64)(u) * ORB_NORB + (o)]
 
+// The per-vertex kernels run one group of G consecutive lanes per vertex
+// (G = 8..64, chosen from the mean degree): low-degree graphs then use
+// all lanes of a wave and reduce over fewer steps.
+template <int G> __device__ inline u32 glane() { return threadIdx.x & (G - 1); }
+template <int G> __device__ inline u64 group_sum_u64(u64 v) {
+    for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
+    return v;
+}
+// Every lane of a wave runs the same number of iterations (vertex u of a
+// group past n is inactive: empty neighbour range, no stores), so the
+// group reductions always see all of their lanes.
+#define GROUP_LOOP(G, u, n)                                                              \
+    for (u64 u##_base = (GTID / WAVE) * (WAVE / (G)); u##_base < (n);                   \
+         u##_base += (GSTRIDE / WAVE) * (WAVE / (G)))                                   \
+        for (u64 u = u##_base + lane_id() / (G), u##_once = 0; u##_once < 1; u##_once++)
+#define GROUP_VALID(u, n) ((u) < (n))
+
 // Tv(u) = number of triangles at u (half the sum of T over u's edges);
 // N1(u) = sum over neighbours v of (d(v) - 1) (orbit 1).
+template <int G>
 __global__ void k_vert0(const u32 *rp, const u32 *ci, const u32 *deg, const u32 *T, u32 n,
                         u64 *Tv, u64 *N1) {
-    for (u64 u = GWAVE; u < n; u += NWAVES) {
+    GROUP_LOOP(G, u, n) {
         u64 t = 0, n1 = 0;
-        for (u32 s = rp[u] + lane_id(); s < rp[u + 1]; s += WAVE) {
+        for (u32 s = (u < n ? rp[u] : 0) + glane<G>(); s < (u < n ? rp[u + 1] : 0); s += G) {
             t += T[s];
             n1 += (u64)deg[ci[s]] - 1;
         }
-        t = wave_sum_u64(t);
-        n1 = wave_sum_u64(n1);
-        if (lane_id() == 0) { Tv[u] = t / 2; N1[u] = n1; }
+        t = group_sum_u64<G>(t);
+        n1 = group_sum_u64<G>(n1);
+        if (glane<G>() == 0 && u < n) { Tv[u] = t / 2; N1[u] = n1; }
     }
 }
 
@@ -26,15 +44,16 @@ __global__ void k_vert0(const u32 *rp, const u32 *ci, const u32 *deg, const u32 
 // orbit equations that sum over triangles (Lemma 4vertexorbit orbit 12;
 // Theorem 5vertexorbit orbits 25, 26, 29, 32, 43, 46, 48, 52, 53, 54, 59,
 // 61, 65).  Each triangle is visited from the slot (u,v) with v < x.
+template <int G>
 __global__ void k_trisweep(const u32 *rp, const u32 *ci, const u32 *src, const u32 *rev,
                            const u32 *deg, const u32 *T, const u64 *tl_ptr, const uint2 *tl,
                            const u64 *Tv, const u64 *N1, const u64 *E7, const u64 *E9,
                            const u64 *C4e, const u64 *K4e, u32 n, u64 *ni) {
-    for (u64 u = GWAVE; u < n; u += NWAVES) {
+    GROUP_LOOP(G, u, n) {
         u64 a12 = 0, a25 = 0, a26 = 0, a29 = 0, a32 = 0, a43 = 0, a46 = 0, a48 = 0, a52 = 0,
             a53 = 0, a54 = 0, a59 = 0, a61 = 0, a65 = 0;
-        const u64 du = deg[u];
-        for (u32 s = rp[u] + lane_id(); s < rp[u + 1]; s += WAVE) {
+        const u64 du = u < n ? deg[u] : 0;
+        for (u32 s = (u < n ? rp[u] : 0) + glane<G>(); s < (u < n ? rp[u + 1] : 0); s += G) {
             const u32 v = ci[s];
             const u32 tuv = T[s];
             if (tuv == 0) continue;
@@ -66,12 +85,12 @@ __global__ void k_trisweep(const u32 *rp, const u32 *ci, const u32 *src, const u
                 a65 += K4e[svx];
             }
         }
-        a12 = wave_sum_u64(a12); a25 = wave_sum_u64(a25); a26 = wave_sum_u64(a26);
-        a29 = wave_sum_u64(a29); a32 = wave_sum_u64(a32); a43 = wave_sum_u64(a43);
-        a46 = wave_sum_u64(a46); a48 = wave_sum_u64(a48); a52 = wave_sum_u64(a52);
-        a53 = wave_sum_u64(a53); a54 = wave_sum_u64(a54); a59 = wave_sum_u64(a59);
-        a61 = wave_sum_u64(a61); a65 = wave_sum_u64(a65);
-        if (lane_id() == 0) {
+        a12 = group_sum_u64<G>(a12); a25 = group_sum_u64<G>(a25); a26 = group_sum_u64<G>(a26);
+        a29 = group_sum_u64<G>(a29); a32 = group_sum_u64<G>(a32); a43 = group_sum_u64<G>(a43);
+        a46 = group_sum_u64<G>(a46); a48 = group_sum_u64<G>(a48); a52 = group_sum_u64<G>(a52);
+        a53 = group_sum_u64<G>(a53); a54 = group_sum_u64<G>(a54); a59 = group_sum_u64<G>(a59);
+        a61 = group_sum_u64<G>(a61); a65 = group_sum_u64<G>(a65);
+        if (glane<G>() == 0 && u < n) {
             NI(u, 12) = a12; NI(u, 25) = a25; NI(u, 26) = a26; NI(u, 29) = a29;
             NI(u, 32) = a32; NI(u, 43) = a43; NI(u, 46) = a46; NI(u, 48) = a48;
             NI(u, 52) = a52; NI(u, 53) = a53; NI(u, 54) = a54; NI(u, 59) = a59;
@@ -85,15 +104,16 @@ __global__ void k_trisweep(const u32 *rp, const u32 *ci, const u32 *src, const u
 // the columns of the orbits they feed (28, 31, 37, 56, 60).  Orbit 69 of u
 // is half the sum, over arcs (v,u), of Q(v,u); the sum is even and is
 // accumulated in 128 bits so that the halving is exact modulo 2^64.
+template <int G>
 __global__ void k_vert1(const u32 *rp, const u32 *ci, const u32 *rev, const u32 *deg,
                         const u32 *T, const u64 *Tv, const u64 *N1, const u64 *C4v,
                         const u64 *K4v, const u64 *C4e, const u64 *K4e, const u64 *E9,
                         const u64 *Q, u32 n, u64 *ni) {
-    for (u64 u = GWAVE; u < n; u += NWAVES) {
-        const u64 du = deg[u];
+    GROUP_LOOP(G, u, n) {
+        const u64 du = u < n ? deg[u] : 0;
         u64 s4 = 0, n6 = 0, n9 = 0, n10 = 0, n13 = 0, s28 = 0, s31 = 0, n22 = 0, s37 = 0,
             n40 = 0, n41 = 0, n55 = 0, s56 = 0, n57 = 0, s60 = 0, n67 = 0, qlo = 0, qhi = 0;
-        for (u32 s = rp[u] + lane_id(); s < rp[u + 1]; s += WAVE) {
+        for (u32 s = (u < n ? rp[u] : 0) + glane<G>(); s < (u < n ? rp[u + 1] : 0); s += G) {
             const u32 v = ci[s];
             const u64 dv = deg[v];
             const u64 t = T[s];
@@ -119,20 +139,20 @@ __global__ void k_vert1(const u32 *rp, const u32 *ci, const u32 *rev, const u32 
             qlo += q;
             qhi += qlo < q;
         }
-        s4 = wave_sum_u64(s4); n6 = wave_sum_u64(n6); n9 = wave_sum_u64(n9);
-        n10 = wave_sum_u64(n10); n13 = wave_sum_u64(n13); s28 = wave_sum_u64(s28);
-        s31 = wave_sum_u64(s31); n22 = wave_sum_u64(n22); s37 = wave_sum_u64(s37);
-        n40 = wave_sum_u64(n40); n41 = wave_sum_u64(n41); n55 = wave_sum_u64(n55);
-        s56 = wave_sum_u64(s56); n57 = wave_sum_u64(n57); s60 = wave_sum_u64(s60);
-        n67 = wave_sum_u64(n67);
+        s4 = group_sum_u64<G>(s4); n6 = group_sum_u64<G>(n6); n9 = group_sum_u64<G>(n9);
+        n10 = group_sum_u64<G>(n10); n13 = group_sum_u64<G>(n13); s28 = group_sum_u64<G>(s28);
+        s31 = group_sum_u64<G>(s31); n22 = group_sum_u64<G>(n22); s37 = group_sum_u64<G>(s37);
+        n40 = group_sum_u64<G>(n40); n41 = group_sum_u64<G>(n41); n55 = group_sum_u64<G>(n55);
+        s56 = group_sum_u64<G>(s56); n57 = group_sum_u64<G>(n57); s60 = group_sum_u64<G>(s60);
+        n67 = group_sum_u64<G>(n67);
         // 128-bit sum of Q: add the lane partials pairwise with carries
-        for (int off = WAVE / 2; off > 0; off >>= 1) {
+        for (int off = G / 2; off > 0; off >>= 1) {
             u64 olo = __shfl_xor(qlo, off, WAVE), ohi = __shfl_xor(qhi, off, WAVE);
             u64 nlo = qlo + olo;
             qhi = qhi + ohi + (nlo < qlo);
             qlo = nlo;
         }
-        if (lane_id() == 0) {
+        if (glane<G>() == 0 && u < n) {
             const u64 n1 = N1[u], t = Tv[u];
             const u64 n2 = c2((i64)du), n3 = t;
             NI(u, 0) = du;
@@ -170,11 +190,12 @@ __global__ void k_vert1(const u32 *rp, const u32 *ci, const u32 *rev, const u32 
 // 66, 68, 69 that the transcribed equations need), finishing the
 // non-induced counts of orbits 15..72 of u.  Reads only columns 4..13 of
 // the neighbours' rows, and writes only columns 15..72 of its own row.
+template <int G>
 __global__ void k_vert2(const u32 *rp, const u32 *ci, const u32 *deg, const u64 *Tv,
                         const u64 *N1, u32 n, u64 *ni) {
-    for (u64 u = GWAVE; u < n; u += NWAVES) {
+    GROUP_LOOP(G, u, n) {
         u64 s15 = 0, s18 = 0, s19 = 0, s24 = 0, s27 = 0, s35 = 0, s39 = 0, s45 = 0;
-        for (u32 s = rp[u] + lane_id(); s < rp[u + 1]; s += WAVE) {
+        for (u32 s = (u < n ? rp[u] : 0) + glane<G>(); s < (u < n ? rp[u + 1] : 0); s += G) {
             const u64 *r = ni + (u64)ci[s] * ORB_NORB;
             s15 += r[4];
             s19 += r[5];
@@ -185,10 +206,10 @@ __global__ void k_vert2(const u32 *rp, const u32 *ci, const u32 *deg, const u64 
             s45 += r[12];
             s39 += r[13];
         }
-        s15 = wave_sum_u64(s15); s18 = wave_sum_u64(s18); s19 = wave_sum_u64(s19);
-        s24 = wave_sum_u64(s24); s27 = wave_sum_u64(s27); s35 = wave_sum_u64(s35);
-        s39 = wave_sum_u64(s39); s45 = wave_sum_u64(s45);
-        if (lane_id() != 0) continue;
+        s15 = group_sum_u64<G>(s15); s18 = group_sum_u64<G>(s18); s19 = group_sum_u64<G>(s19);
+        s24 = group_sum_u64<G>(s24); s27 = group_sum_u64<G>(s27); s35 = group_sum_u64<G>(s35);
+        s39 = group_sum_u64<G>(s39); s45 = group_sum_u64<G>(s45);
+        if (glane<G>() != 0 || u >= n) continue;
         u64 *R = ni + u * ORB_NORB;
         const u64 d = deg[u];
         const u64 n1 = N1[u], t = Tv[u];
@@ -248,12 +269,23 @@ __global__ void k_vert2(const u32 *rp, const u32 *ci, const u32 *deg, const u64 
 
 // Induced counts: I = Ainv N per row, block by block; Ainv is unit upper
 // triangular, so row i only reads columns >= i and can be overwritten in
-// increasing order.  Writes the first K columns of every row to out (which
-// may alias ni when K == 73).
-__global__ void k_transform(u64 *ni, u32 n, int K, int induced, u64 *out) {
-    for (u64 u = GTID; u < n; u += GSTRIDE) {
-        u64 *R = ni + u * ORB_NORB;
-        if (induced) {
+// increasing order.  One wave per tile of 64 rows: the rows are read into
+// LDS with coalesced loads, each lane transforms one row there (a row's
+// 73 words are 584 bytes apart from the next lane's, so the LDS reads are
+// spread over all banks), and the first K columns go out with coalesced
+// stores (out may alias ni when K == 73).
+#define XF_ROWS 64
+__global__ void __launch_bounds__(WAVE) k_transform(u64 *ni, u32 n, int K, int induced,
+                                                    u64 *out) {
+    __shared__ u64 tile[XF_ROWS * ORB_NORB];
+    const u32 lane = threadIdx.x;
+    for (u64 base = (u64)blockIdx.x * XF_ROWS; base < n; base += (u64)gridDim.x * XF_ROWS) {
+        const u32 rows = n - base < XF_ROWS ? (u32)(n - base) : XF_ROWS;
+        const u64 *src = ni + base * ORB_NORB;
+        for (u32 i = lane; i < rows * ORB_NORB; i += WAVE) tile[i] = src[i];
+        __syncthreads();
+        if (induced && lane < rows) {
+            u64 *R = tile + (u64)lane * ORB_NORB;
             for (int i = 0; i < K; i++) {
                 u64 acc = 0;
                 for (int k = ORB_AINV_PTR[i]; k < ORB_AINV_PTR[i + 1]; k++)
@@ -261,8 +293,15 @@ __global__ void k_transform(u64 *ni, u32 n, int K, int induced, u64 *out) {
                 R[i] = acc;
             }
         }
-        if (out != ni || K != ORB_NORB)
-            for (int i = 0; i < K; i++) out[u * K + i] = R[i];
+        __syncthreads();
+        u64 *dst = out + base * K;
+        if (K == ORB_NORB) {
+            for (u32 i = lane; i < rows * ORB_NORB; i += WAVE) dst[i] = tile[i];
+        } else {
+            for (u32 i = lane; i < rows * (u32)K; i += WAVE)
+                dst[i] = tile[(i / K) * ORB_NORB + i % K];
+        }
+        __syncthreads();
     }
 }
 

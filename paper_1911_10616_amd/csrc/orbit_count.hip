@@ -258,16 +258,58 @@ __global__ void k_edge_e7e9(const u32 *src, const u32 *ci, const u32 *rev, const
 // One workgroup per source vertex at a time (dynamic), with dense per-WG
 // scratch arrays indexed by vertex id that are restored to zero after
 // every source.
-// The sources come from a queue: the i-th fetch gets order[i] (a schedule),
-// or i itself when there is no schedule; n once the queue is empty.
-__device__ inline u32 next_source(u32 *counter, u32 *sh, const u32 *order, u32 n) {
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        u32 i = atomicAdd(counter, 1u);
-        *sh = i < n ? (order ? order[i] : i) : n;
+// Execution group of a per-source kernel: the whole workgroup works on one
+// source (GpWG: heavy sources, big graphs), or each wave works on its own
+// source with its own scratch (GpWave: many light sources, small graphs).
+struct GpWG {
+    static constexpr u32 size = WG, per_wg = 1, chunk = 1;
+    __device__ static u32 id() { return 0; }
+    __device__ static u32 rank() { return threadIdx.x; }
+    __device__ static u64 global_id() { return blockIdx.x; }
+    __device__ static void sync() { __syncthreads(); }
+    __device__ static u64 sum(u64 v, u64 *sh) {
+        v = wave_sum_u64(v);
+        __syncthreads();
+        if (lane_id() == 0) sh[wave_in_wg()] = v;
+        __syncthreads();
+        u64 t = 0;
+        for (int w = 0; w < WAVES_PER_WG; w++) t += sh[w];
+        return t;
     }
-    __syncthreads();
-    return *sh;
+};
+struct GpWave {
+    static constexpr u32 size = WAVE, per_wg = WAVES_PER_WG, chunk = 16;
+    __device__ static u32 id() { return wave_in_wg(); }
+    __device__ static u32 rank() { return lane_id(); }
+    __device__ static u64 global_id() { return (u64)blockIdx.x * per_wg + wave_in_wg(); }
+    __device__ static void sync() {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    }
+    __device__ static u64 sum(u64 v, u64 *) { return wave_sum_u64(v); }
+};
+
+// The sources come from a queue: the i-th entry is order[i] (a schedule),
+// or i itself when there is no schedule; n once the queue is empty.  A group
+// takes GP::chunk consecutive entries per atomic on the shared counter (light
+// sources would otherwise serialise on it).  q[0..1] = the group's current
+// range of queue entries, q[2] = the source handed out; both start at 0.
+template <class GP>
+__device__ inline u32 next_source(u32 *counter, u32 *q, const u32 *order, u32 n) {
+    GP::sync();
+    if (GP::rank() == 0) {
+        if (q[0] >= q[1]) {
+            const u32 i = atomicAdd(counter, GP::chunk);
+            q[0] = i;
+            q[1] = i < n ? (n - i < GP::chunk ? n : i + GP::chunk) : i;
+        }
+        const u32 i = q[0];
+        q[2] = i < q[1] ? (order ? order[i] : i) : n;
+        q[0] = i + 1;
+    }
+    GP::sync();
+    return q[2];
 }
 
 // Dynamic loop of a wave over [0, count): items are taken from an LDS
@@ -298,23 +340,28 @@ __device__ inline u64 block_sum_u64(u64 v, u64 *sh) {
 // Every 4-cycle has a unique top x and opposite z; it adds C(cnt,2) to x and
 // z, cnt-1 to each middle y, and cnt-1 to the edges (x,y) and (y,z).
 // Gives C4(u) (orbit 8) and C4(e) (edge orbit E5).
+template <class GP>
 __global__ void __launch_bounds__(WG) k_c4(const u32 *rp, const u32 *ci, const u32 *rev,
                                           const u64 *key, u32 n, unsigned char *scratch,
                                           u64 stride, u32 *work, const u32 *order, u32 mapn,
                                           const u32 *gbase, u64 *C4v, u64 *C4e) {
-    __shared__ u32 sh_src, sh_nt, sh_next;
+    __shared__ u32 sh_q_[GP::per_wg][3], sh_nt_[GP::per_wg], sh_next_[GP::per_wg];
+    u32 *sh_q = sh_q_[GP::id()];
+    if (GP::rank() == 0) { sh_q[0] = 0; sh_q[1] = 0; }
+    u32 &sh_nt = sh_nt_[GP::id()];
+    u32 &sh_next = sh_next_[GP::id()];
     __shared__ u64 sh_red[WAVES_PER_WG];
-    unsigned char *base = scratch + (u64)blockIdx.x * stride;
+    unsigned char *base = scratch + GP::global_id() * stride;
     u32 *cnt = (u32 *)base;
     u32 *touched = (u32 *)align256((unsigned char *)(cnt + mapn));
     for (;;) {
-        u32 x = next_source(work, &sh_src, order, n);
+        u32 x = next_source<GP>(work, sh_q, order, n);
         if (x >= n) break;
         const u32 vb = gbase ? gbase[x] : 0;  // maps are indexed within x's graph
         const u64 kx = key[x];
         const u32 bx = rp[x], dx = rp[x + 1] - bx;
-        if (threadIdx.x == 0) { sh_nt = 0; sh_next = 0; }
-        __syncthreads();
+        if (GP::rank() == 0) { sh_nt = 0; sh_next = 0; }
+        GP::sync();
         wave_loop(&sh_next, dx, [&](u32 i) {
             u32 y = ci[bx + i];
             if (key[y] >= kx) return;
@@ -326,18 +373,18 @@ __global__ void __launch_bounds__(WG) k_c4(const u32 *rp, const u32 *ci, const u
                 }
             }
         });
-        __syncthreads();
+        GP::sync();
         const u32 nt = sh_nt;
         u64 loc = 0;
-        for (u32 t = threadIdx.x; t < nt; t += WG) {
+        for (u32 t = GP::rank(); t < nt; t += GP::size) {
             u32 z = touched[t];
             u64 v = c2(cnt[z - vb]);
             loc += v;
             atomic_add_u64(&C4v[z], v);
         }
-        u64 tot = block_sum_u64(loc, sh_red);
-        if (threadIdx.x == 0) { atomic_add_u64(&C4v[x], tot); sh_next = 0; }
-        __syncthreads();
+        u64 tot = GP::sum(loc, sh_red);
+        if (GP::rank() == 0) { atomic_add_u64(&C4v[x], tot); sh_next = 0; }
+        GP::sync();
         wave_loop(&sh_next, dx, [&](u32 i) {
             u32 sxy = bx + i;
             u32 y = ci[sxy];
@@ -361,8 +408,8 @@ __global__ void __launch_bounds__(WG) k_c4(const u32 *rp, const u32 *ci, const u
                 atomicAdd(&C4e[rev[sxy]], acc);
             }
         });
-        __syncthreads();
-        for (u32 t = threadIdx.x; t < nt; t += WG) cnt[touched[t] - vb] = 0;
+        GP::sync();
+        for (u32 t = GP::rank(); t < nt; t += GP::size) cnt[touched[t] - vb] = 0;
     }
 }
 
@@ -379,6 +426,10 @@ __global__ void __launch_bounds__(WG) k_c4(const u32 *rp, const u32 *ci, const u
 //           triangle) - 1 (Theorem 5vertexorbit), needing the final K4(t).
 #define CLQ_LDS_D 384
 #define CLQ_LDS_W (CLQ_LDS_D / 64)
+// u64 words of one execution group's LDS rows for out-degrees up to d
+__host__ __device__ inline u64 clique_lds_words(u32 d) {
+    return 2ull * d + 2ull * d * ((d + 63) / 64) + (d + 1) / 2;
+}
 
 __device__ inline u64 tri_find(u64 arc, u32 z, const u64 *tri_ptr, const u32 *tri_c,
                                DevState *st) {
@@ -397,23 +448,29 @@ __device__ inline u64 arc_find(u32 x, u32 y, const u64 *out_ptr, const u32 *out_
     return b + i;
 }
 
+template <class GP>
 __global__ void __launch_bounds__(WG) k_clique(int pass, u32 n, const u32 *rev,
                                               const u64 *out_ptr, const u32 *out_nbr,
                                               const u32 *out_slot, const u64 *tri_ptr,
                                               const u32 *tri_c, const u32 *tri_sbc,
                                               unsigned char *scratch, u64 stride, u32 dcap,
-                                              u32 *work, const u32 *order, u32 *K4t, u64 *K4v,
-                                              u64 *K4e, u64 *ni, DevState *st) {
-    __shared__ u32 sh_src, sh_next;
+                                              u32 lds_d, u32 *work, const u32 *order, u32 *K4t,
+                                              u64 *K4v, u64 *K4e, u64 *ni, DevState *st) {
+    __shared__ u32 sh_q_[GP::per_wg][3], sh_next_[GP::per_wg];
+    u32 *sh_q = sh_q_[GP::id()];
+    if (GP::rank() == 0) { sh_q[0] = 0; sh_q[1] = 0; }
+    u32 &sh_next = sh_next_[GP::id()];
     __shared__ u64 sh_red[WAVES_PER_WG];
-    __shared__ u32 l_nbr[CLQ_LDS_D];
-    __shared__ u64 l_und[CLQ_LDS_D * CLQ_LDS_W];
-    __shared__ u64 l_out[CLQ_LDS_D * CLQ_LDS_W];
-    __shared__ u64 l_acc[CLQ_LDS_D];
-    __shared__ u64 l_acc5[CLQ_LDS_D];
-    unsigned char *gbase = scratch + (u64)blockIdx.x * stride;
+    // dynamic LDS: acc, acc5 [lds_d]; und, outm [lds_d * lds_w]; nbr [lds_d]
+    // (one such set per execution group)
+    extern __shared__ u64 dyn_lds[];
+    const u32 lds_w = (lds_d + 63) / 64;
+    u64 *l_acc = dyn_lds + (u64)GP::id() * clique_lds_words(lds_d), *l_acc5 = l_acc + lds_d;
+    u64 *l_und = l_acc5 + lds_d, *l_out = l_und + (u64)lds_d * lds_w;
+    u32 *l_nbr = (u32 *)(l_out + (u64)lds_d * lds_w);
+    unsigned char *gbase = scratch + GP::global_id() * stride;
     for (;;) {
-        u32 a = next_source(work, &sh_src, order, n);
+        u32 a = next_source<GP>(work, sh_q, order, n);
         if (a >= n) break;
         const u64 pa = out_ptr[a];
         const u32 D = (u32)(out_ptr[a + 1] - pa);
@@ -421,11 +478,11 @@ __global__ void __launch_bounds__(WG) k_clique(int pass, u32 n, const u32 *rev,
         const u32 W = (D + 63) / 64;
         u32 *nbr;
         u64 *und, *outm, *acc, *acc5;
-        if (D <= CLQ_LDS_D) {
+        if (D <= lds_d) {
             nbr = l_nbr; und = l_und; outm = l_out; acc = l_acc; acc5 = l_acc5;
         } else {
             if (D > dcap) {  // cannot happen: out-degrees are bounded by the peel level
-                if (threadIdx.x == 0) atomicOr(&st->err, ERRB_INTERNAL);
+                if (GP::rank() == 0) atomicOr(&st->err, ERRB_INTERNAL);
                 continue;
             }
             nbr = (u32 *)gbase;
@@ -434,14 +491,14 @@ __global__ void __launch_bounds__(WG) k_clique(int pass, u32 n, const u32 *rev,
             acc = outm + (u64)D * W;
             acc5 = acc + D;
         }
-        for (u32 i = threadIdx.x; i < D; i += WG) {
+        for (u32 i = GP::rank(); i < D; i += GP::size) {
             nbr[i] = out_nbr[pa + i];
             acc[i] = 0;
             acc5[i] = 0;
         }
-        for (u32 i = threadIdx.x; i < D * W; i += WG) { und[i] = 0; outm[i] = 0; }
-        if (threadIdx.x == 0) sh_next = 0;
-        __syncthreads();
+        for (u32 i = GP::rank(); i < D * W; i += GP::size) { und[i] = 0; outm[i] = 0; }
+        if (GP::rank() == 0) sh_next = 0;
+        GP::sync();
         wave_loop(&sh_next, D, [&](u32 i) {
             u32 b = nbr[i];
             for (u64 q = out_ptr[b] + lane_id(); q < out_ptr[b + 1]; q += WAVE) {
@@ -453,10 +510,10 @@ __global__ void __launch_bounds__(WG) k_clique(int pass, u32 n, const u32 *rev,
                 }
             }
         });
-        __syncthreads();
+        GP::sync();
         const u64 r0 = tri_ptr[pa], r1 = tri_ptr[pa + D];
         u64 tot = 0, tot5 = 0;
-        for (u64 r = r0 + threadIdx.x; r < r1; r += WG) {
+        for (u64 r = r0 + GP::rank(); r < r1; r += GP::size) {
             // owner arc of record r: largest p in [pa, pa+D) with tri_ptr[p] <= r
             u32 lo = 0, hi = D;
             while (hi - lo > 1) {
@@ -528,10 +585,10 @@ __global__ void __launch_bounds__(WG) k_clique(int pass, u32 n, const u32 *rev,
                 }
             }
         }
-        __syncthreads();
-        u64 t4 = block_sum_u64(tot, sh_red);
-        u64 t5 = pass == 1 ? block_sum_u64(tot5, sh_red) : 0;
-        for (u32 i = threadIdx.x; i < D; i += WG) {
+        GP::sync();
+        u64 t4 = GP::sum(tot, sh_red);
+        u64 t5 = pass == 1 ? GP::sum(tot5, sh_red) : 0;
+        for (u32 i = GP::rank(); i < D; i += GP::size) {
             u32 v = nbr[i];
             if (pass == 1) {
                 u64 h = acc[i] / 2;
@@ -546,7 +603,7 @@ __global__ void __launch_bounds__(WG) k_clique(int pass, u32 n, const u32 *rev,
                 atomic_add_u64(&NI(v, 70), acc[i]);
             }
         }
-        if (threadIdx.x == 0) {
+        if (GP::rank() == 0) {
             if (pass == 1) {
                 atomic_add_u64(&K4v[a], t4 / 3);
                 atomic_add_u64(&NI(a, 72), t5);
@@ -554,7 +611,7 @@ __global__ void __launch_bounds__(WG) k_clique(int pass, u32 n, const u32 *rev,
                 atomic_add_u64(&NI(a, 70), t4);
             }
         }
-        __syncthreads();
+        GP::sync();
     }
 }
 
@@ -621,32 +678,43 @@ __device__ inline PairScratch pair_scratch(unsigned char *base, u32 n) {
     return p;
 }
 
+template <class GP>
 __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, const u32 *src,
                                              const u32 *rev, const u32 *deg, const u32 *T,
                                              const u64 *tl_ptr, const uint2 *tl, u32 n,
                                              unsigned char *scratch, u64 stride, u32 *work,
                                              const u32 *order, u32 mapn, const u32 *gbase,
-                                             u64 *steps, u64 *Q, u64 *ni) {
-    __shared__ u32 sh_src, sh_nt, sh_next;
+                                             u32 kl, u64 *steps, u64 *Q, u64 *ni) {
+    __shared__ u32 sh_q_[GP::per_wg][3], sh_nt_[GP::per_wg], sh_next_[GP::per_wg];
+    u32 *sh_q = sh_q_[GP::id()];
+    if (GP::rank() == 0) { sh_q[0] = 0; sh_q[1] = 0; }
+    u32 &sh_nt = sh_nt_[GP::id()];
+    u32 &sh_next = sh_next_[GP::id()];
     __shared__ u32 sh_ntk[WAVES_PER_WG];
     __shared__ u64 sh_red[WAVES_PER_WG];
-    __shared__ u32 l_k[WAVES_PER_WG][PAIR_KMAP_LDS];
-    __shared__ unsigned short l_tk[WAVES_PER_WG][PAIR_KMAP_LDS];
-    PairScratch P = pair_scratch(scratch + (u64)blockIdx.x * stride, mapn);
+    // dynamic LDS: per-wave wheel maps of kl positions (u32) and touched
+    // lists (u16), kl <= PAIR_KMAP_LDS
+    extern __shared__ u64 dyn_lds[];
+    u32 *l_k0 = (u32 *)dyn_lds;
+    unsigned short *l_tk0 = (unsigned short *)(l_k0 + WAVES_PER_WG * kl);
+    PairScratch P = pair_scratch(scratch + GP::global_id() * stride, mapn);
     u32 *Kw = P.K + (u64)wave_in_wg() * mapn;
     u32 *tkw = P.tk + (u64)wave_in_wg() * mapn;
-    for (u32 i = threadIdx.x; i < WAVES_PER_WG * PAIR_KMAP_LDS; i += WG) (&l_k[0][0])[i] = 0;
+    // every thread of the workgroup clears its share, then all wait (the
+    // slices belong to different waves)
+    for (u32 i = threadIdx.x; i < WAVES_PER_WG * kl; i += WG) l_k0[i] = 0;
+    __syncthreads();
     for (;;) {
-        const u32 a = next_source(work, &sh_src, order, n);
+        const u32 a = next_source<GP>(work, sh_q, order, n);
         if (a >= n) break;
         const u32 vb = gbase ? gbase[a] : 0;  // maps are indexed within a's graph
         const u32 ba = rp[a], da = rp[a + 1] - ba;
         if (da < 2) continue;
         const u64 dega = da;
         u64 nsteps = 0;  // loop iterations of this thread for this source
-        for (u32 i = threadIdx.x; i < da; i += WG) P.mark[ci[ba + i] - vb] = 1;
-        if (threadIdx.x == 0) { sh_nt = 0; sh_next = 0; }
-        __syncthreads();
+        for (u32 i = GP::rank(); i < da; i += GP::size) P.mark[ci[ba + i] - vb] = 1;
+        if (GP::rank() == 0) { sh_nt = 0; sh_next = 0; }
+        GP::sync();
         // wedges a - y - b, b > a
         wave_loop(&sh_next, da, [&](u32 iy) {
             const u32 say = ba + iy, y = ci[say];
@@ -662,9 +730,9 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
                 atomicAdd(&P.TB[b - vb], (u64)T[s]);
             }
         });
-        __syncthreads();
-        if (threadIdx.x == 0) sh_next = 0;
-        __syncthreads();
+        GP::sync();
+        if (GP::rank() == 0) sh_next = 0;
+        GP::sync();
         // wheel maps of the arcs (a, y): K(a,y,b) = |N(a) & N(y) & N(b)| for
         // b > a, from the diamonds with tip a and chord (y,z) (z in the
         // triangle list of (a,y), b in the list of (y,z), which is sorted by
@@ -682,9 +750,9 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
             // the map of (a, y) is indexed by b's position in N(y): in LDS
             // when d(y) fits, else in the wave's global map
             const u32 by = rp[y], dy = rp[y + 1] - by;
-            const bool inl = dy <= PAIR_KMAP_LDS;
-            u32 *kc = inl ? l_k[wave_in_wg()] : Kw;
-            unsigned short *tl_l = l_tk[wave_in_wg()];
+            const bool inl = dy <= kl;
+            u32 *kc = inl ? l_k0 + wave_in_wg() * kl : Kw;
+            unsigned short *tl_l = l_tk0 + wave_in_wg() * kl;
             TLView tv = tl_view(say, src, ci, rev, T, tl_ptr, tl);
             u32 *ntk = &sh_ntk[wave_in_wg()];
             for (u32 k = 0; k < tv.len; k++) {
@@ -733,13 +801,13 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
         });
-        __syncthreads();
+        GP::sync();
         // l68 is uniform within each wave (computed from wave sums)
         if (lane_id() == 0) atomic_add_u64(&NI(a, 68), l68);
         // pair terms (P.E holds 2 e)
         const u32 nt = sh_nt;
         u64 l36 = 0, l50 = 0, l51 = 0, l63 = 0;
-        for (u32 t = threadIdx.x; t < nt; t += WG) {
+        for (u32 t = GP::rank(); t < nt; t += GP::size) {
             const u32 b = P.touched[t];
             const u64 s = P.S[b - vb];
             if (s < 2) continue;
@@ -755,18 +823,18 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
             atomic_add_u64(&NI(b, 51), (P.TA[b - vb] - adj * s) * (s - 1));
             atomic_add_u64(&NI(b, 63), e * (s - 2));
         }
-        l36 = block_sum_u64(l36, sh_red);
-        l50 = block_sum_u64(l50, sh_red);
-        l51 = block_sum_u64(l51, sh_red);
-        l63 = block_sum_u64(l63, sh_red);
-        if (threadIdx.x == 0) {
+        l36 = GP::sum(l36, sh_red);
+        l50 = GP::sum(l50, sh_red);
+        l51 = GP::sum(l51, sh_red);
+        l63 = GP::sum(l63, sh_red);
+        if (GP::rank() == 0) {
             atomic_add_u64(&NI(a, 36), l36);
             atomic_add_u64(&NI(a, 50), l50);
             atomic_add_u64(&NI(a, 51), l51);
             atomic_add_u64(&NI(a, 63), l63);
             sh_next = 0;
         }
-        __syncthreads();
+        GP::sync();
         // centre terms
         wave_loop(&sh_next, da, [&](u32 iy) {
             const u32 say = ba + iy, y = ci[say];
@@ -789,17 +857,17 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
                 atomic_add_u64(&NI(y, 62), a62);
             }
         });
-        __syncthreads();
-        for (u32 t = threadIdx.x; t < nt; t += WG) {
+        GP::sync();
+        for (u32 t = GP::rank(); t < nt; t += GP::size) {
             const u32 b = P.touched[t];
             P.S[b - vb] = 0; P.E[b - vb] = 0; P.TA[b - vb] = 0; P.TB[b - vb] = 0;
         }
-        for (u32 i = threadIdx.x; i < da; i += WG) P.mark[ci[ba + i] - vb] = 0;
+        for (u32 i = GP::rank(); i < da; i += GP::size) P.mark[ci[ba + i] - vb] = 0;
         if (steps) {  // per-source work, the training target of the scheduler
-            u64 tot = block_sum_u64(nsteps, sh_red);
-            if (threadIdx.x == 0) steps[a] += tot;
+            u64 tot = GP::sum(nsteps, sh_red);
+            if (GP::rank() == 0) steps[a] += tot;
         }
-        __syncthreads();
+        GP::sync();
     }
 }
 
@@ -832,26 +900,31 @@ __device__ inline bool out_adjacent(u32 k, u32 i, const u64 *out_ptr, const u32 
     return bfind(out_nbr + b, (u32)(out_ptr[k + 1] - b), i) != UNSET;
 }
 
+template <class GP>
 __global__ void __launch_bounds__(WG) k_c5(const u32 *rp, const u32 *ci, const u64 *key,
                                           const u64 *out_ptr, const u32 *out_nbr,
                                           const u32 *out_slot, const u32 *Tin, const u32 *Tmid,
                                           u32 n, unsigned char *scratch, u64 stride, u32 *work,
                                           const u32 *order, u32 mapn, const u32 *gbase,
                                           u64 *steps, u64 *ni) {
-    __shared__ u32 sh_src, sh_nt, sh_next;
+    __shared__ u32 sh_q_[GP::per_wg][3], sh_nt_[GP::per_wg], sh_next_[GP::per_wg];
+    u32 *sh_q = sh_q_[GP::id()];
+    if (GP::rank() == 0) { sh_q[0] = 0; sh_q[1] = 0; }
+    u32 &sh_nt = sh_nt_[GP::id()];
+    u32 &sh_next = sh_next_[GP::id()];
     __shared__ u64 sh_red[WAVES_PER_WG];
-    C5Scratch C = c5_scratch(scratch + (u64)blockIdx.x * stride, mapn);
+    C5Scratch C = c5_scratch(scratch + GP::global_id() * stride, mapn);
     for (;;) {
-        const u32 l = next_source(work, &sh_src, order, n);
+        const u32 l = next_source<GP>(work, sh_q, order, n);
         if (l >= n) break;
         const u32 vb = gbase ? gbase[l] : 0;  // maps are indexed within l's graph
         const u32 bl = rp[l], dl = rp[l + 1] - bl;
         if (dl < 2) continue;
         const u64 kl = key[l];
         u64 nsteps = 0;  // loop iterations of this thread for this source
-        for (u32 i = threadIdx.x; i < dl; i += WG) C.mark[ci[bl + i] - vb] = 1;
-        if (threadIdx.x == 0) { sh_nt = 0; sh_next = 0; }
-        __syncthreads();
+        for (u32 i = GP::rank(); i < dl; i += GP::size) C.mark[ci[bl + i] - vb] = 1;
+        if (GP::rank() == 0) { sh_nt = 0; sh_next = 0; }
+        GP::sync();
         // non-in-in wedges l - w - i, and 3-paths i <- j <- k -> l
         wave_loop(&sh_next, dl, [&](u32 iw) {
             const u32 w = ci[bl + iw];
@@ -884,9 +957,9 @@ __global__ void __launch_bounds__(WG) k_c5(const u32 *rp, const u32 *ci, const u
                 }
             }
         });
-        __syncthreads();
-        if (threadIdx.x == 0) sh_next = 0;
-        __syncthreads();
+        GP::sync();
+        if (GP::rank() == 0) sh_next = 0;
+        GP::sync();
         // credits of j and k per 3-path, and of w per wedge
         wave_loop(&sh_next, dl, [&](u32 iw) {
             const u32 slw = bl + iw;
@@ -937,30 +1010,30 @@ __global__ void __launch_bounds__(WG) k_c5(const u32 *rp, const u32 *ci, const u
             accw = wave_sum_u64(accw);
             if (lane_id() == 0) atomic_add_u64(&NI(w, 34), accw);
         });
-        __syncthreads();
+        GP::sync();
         // credits of i (summed over its 3-paths) and of l
         const u32 nt = sh_nt;
         u64 accl = 0;
-        for (u32 t = threadIdx.x; t < nt; t += WG) {
+        for (u32 t = GP::rank(); t < nt; t += GP::size) {
             const u32 i = C.touched[t];
             const u64 v = C.P[i - vb] * (u64)C.Wm[i - vb] - C.CI[i - vb];
             accl += v;
             atomic_add_u64(&NI(i, 34), v);
         }
-        accl = block_sum_u64(accl, sh_red);
-        if (threadIdx.x == 0) atomic_add_u64(&NI(l, 34), accl);
+        accl = GP::sum(accl, sh_red);
+        if (GP::rank() == 0) atomic_add_u64(&NI(l, 34), accl);
         if (steps) {
-            const u64 tot = block_sum_u64(nsteps, sh_red);
-            if (threadIdx.x == 0) steps[l] += tot;
+            const u64 tot = GP::sum(nsteps, sh_red);
+            if (GP::rank() == 0) steps[l] += tot;
         }
-        __syncthreads();
+        GP::sync();
         // reset: Wm was touched on every wedge endpoint, P/CI on 3-path ends
-        for (u32 t = threadIdx.x; t < nt; t += WG) {
+        for (u32 t = GP::rank(); t < nt; t += GP::size) {
             const u32 i = C.touched[t];
             C.P[i - vb] = 0; C.CI[i - vb] = 0;
         }
-        if (threadIdx.x == 0) sh_next = 0;
-        __syncthreads();
+        if (GP::rank() == 0) sh_next = 0;
+        GP::sync();
         wave_loop(&sh_next, dl, [&](u32 iw) {
             const u32 w = ci[bl + iw];
             if (key[w] > kl) {
@@ -969,7 +1042,7 @@ __global__ void __launch_bounds__(WG) k_c5(const u32 *rp, const u32 *ci, const u
                 for (u32 s = rp[w] + lane_id(); s < rp[w + 1]; s += WAVE) C.Wm[ci[s] - vb] = 0;
             }
         });
-        for (u32 i = threadIdx.x; i < dl; i += WG) C.mark[ci[bl + i] - vb] = 0;
-        __syncthreads();
+        for (u32 i = GP::rank(); i < dl; i += GP::size) C.mark[ci[bl + i] - vb] = 0;
+        GP::sync();
     }
 }

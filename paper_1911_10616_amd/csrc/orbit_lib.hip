@@ -6,6 +6,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <new>
+
 #include "orbit_common.h"
 #include "orbit_prep.hip"
 #include "orbit_count.hip"
@@ -16,6 +18,11 @@
 namespace {
 
 const int kMaxPhases = 24;
+// auto: wave groups when the maps are at most this big and the out-degrees
+// (bounded by the degeneracy) this small, i.e. when every source is light
+const u32 kWaveGroupMaxMap = 4096;
+const u32 kWaveGroupMaxOut = 64;
+const u64 kMaxDynLds = 64 << 10;  // dynamic LDS per workgroup
 thread_local float g_phase_ms[kMaxPhases];
 thread_local const char *g_phase_name[kMaxPhases];
 thread_local int g_nphase = 0;
@@ -39,6 +46,7 @@ struct Layout {
     u64 total = 0;
     u64 stride = 0;
     u32 nwg = 0;
+    u32 per_wg = 1;  // execution groups (each with its own scratch) per workgroup
 };
 
 u64 align_up(u64 x, u64 a) { return (x + a - 1) / a * a; }
@@ -88,7 +96,7 @@ u64 clique_stride(u32 dmax) {
 // mapn: size of the per-source maps -- n, or the largest graph of a batch
 // (maps are then indexed by position within the source's graph).
 void layout_phase2(Layout &L, u32 n, u32 mapn, u64 m, u64 ntri, u32 dmax, int k_max,
-                   bool ni_in_out, u32 nwg_req) {
+                   bool ni_in_out, u32 nwg_req, u32 per_wg) {
     const u64 M2 = 2 * m;
     u64 c = L.p1_end;
     place(c, L.tri_c, 4ull * (ntri + 1));
@@ -129,10 +137,11 @@ void layout_phase2(Layout &L, u32 n, u32 mapn, u64 m, u64 ntri, u32 dmax, int k_
     u32 nwg = nwg_req ? nwg_req : 512;
     // keep the per-source scratch within 48 GiB unless asked otherwise
     const u64 cap = 48ull << 30;
-    while (!nwg_req && nwg > 64 && (u64)nwg * stride > cap) nwg /= 2;
+    while (!nwg_req && nwg > 64 && (u64)nwg * per_wg * stride > cap) nwg /= 2;
     L.nwg = nwg;
+    L.per_wg = per_wg;
     L.stride = stride;
-    place(c, L.scratch, (u64)nwg * stride);
+    place(c, L.scratch, (u64)nwg * per_wg * stride);
     L.total = align_up(c, 256);
 }
 
@@ -163,6 +172,14 @@ int err_to_status(u32 e) {
 // needs to be zero when it starts; it restores them to zero itself, but the
 // lists it leaves behind are not zero, so the ranges are cleared before
 // every such kernel.  Mirrors the device-side carving (base is 256-aligned).
+unsigned grid_for(u64 items, unsigned per_block) {
+    u64 g = (items + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > 8192) g = 8192;
+    return (unsigned)g;
+}
+unsigned grid_waves(u64 items) { return grid_for(items * WAVE, WG); }
+
 struct ZeroRange {
     u64 off, len;
 };
@@ -189,17 +206,38 @@ int zero_scratch(int which, u32 mapn, unsigned char *scratch, const Layout &L, u
     ZeroRange r[2];
     int k = zero_ranges(which, mapn, r);
     for (int i = 0; i < k; i++)
-        HCHK(hipMemset2DAsync(scratch + r[i].off, L.stride, 0, r[i].len, nwg, s));
+        k_zero_rows<<<grid_for(r[i].len / 8 * nwg, WG), WG, 0, s>>>(scratch + r[i].off, L.stride,
+                                                                   r[i].len / 8, nwg);
+    HCHK(hipGetLastError());
     return ORB_OK;
 }
 
-unsigned grid_for(u64 items, unsigned per_block) {
-    u64 g = (items + per_block - 1) / per_block;
-    if (g < 1) g = 1;
-    if (g > 8192) g = 8192;
-    return (unsigned)g;
+
+
+// Lanes per vertex in the per-vertex kernels, from the mean degree: small
+// groups for sparse low-degree graphs, whole waves otherwise.
+int group_size(u32 n, u64 m) {
+    const u64 mean_deg = n ? (2 * m) / n : 0;
+    return mean_deg <= 8 ? 8 : mean_deg <= 16 ? 16 : 64;
 }
-unsigned grid_waves(u64 items) { return grid_for(items * WAVE, WG); }
+
+// Launches the statement with the per-source execution group GPT.
+#define WITH_GP(wave, ...)                                  \
+    do {                                                    \
+        if (wave) { using GPT = GpWave; __VA_ARGS__; }      \
+        else { using GPT = GpWG; __VA_ARGS__; }             \
+    } while (0)
+
+// Launches the statement with the compile-time lane-group size GG = g.
+#define WITH_GROUP(g, ...)                                      \
+    do {                                                        \
+        switch (g) {                                            \
+            case 8: { constexpr int GG = 8; __VA_ARGS__; } break;   \
+            case 16: { constexpr int GG = 16; __VA_ARGS__; } break; \
+            case 32: { constexpr int GG = 32; __VA_ARGS__; } break; \
+            default: { constexpr int GG = 64; __VA_ARGS__; } break; \
+        }                                                       \
+    } while (0)
 
 struct Timer {
     bool on;
@@ -256,10 +294,30 @@ int read_state(DevState *d, DevState *h, hipStream_t s) {
     return ORB_OK;
 }
 
+// A plan: a graph of the whole count, captured after one ordinary run that
+// fixed the data-dependent choices (peel launches, triangle count,
+// degeneracy, largest graph of a batch).  While capturing, nothing is read
+// back to the host.
+struct Plan {
+    bool capture = false;
+    int peel_groups = 0;
+    u64 ntri = 0;
+    u32 maxlevel = 0, gmax = 0;
+};
+
+// zero n64 u64 words at p (a kernel, capturable)
+int zero_u64(void *p, u64 n64, hipStream_t s) {
+    if (!n64) return ORB_OK;
+    k_fill_u64<<<grid_for(n64, WG), WG, 0, s>>>((u64 *)p, n64, 0);
+    HCHK(hipGetLastError());
+    return ORB_OK;
+}
+
 // Phase 1: validation, peeling, orientation and triangle counting.  Leaves
 // ntri and the degeneracy in *hs.
 int run_phase1(const u32 *rp, const u32 *ci, u32 n, u64 m, const u64 *vptr, u32 B, void *ws,
-               const Layout &L, hipStream_t s, DevState *hs, Timer &tm) {
+               const Layout &L, hipStream_t s, DevState *hs, Timer &tm, Plan *pl) {
+    const bool cap = pl && pl->capture;
     const u64 M2 = 2 * m;
     DevState *st = at<DevState>(ws, L.state);
     u32 *deg = at<u32>(ws, L.deg), *src = at<u32>(ws, L.src), *rev = at<u32>(ws, L.rev);
@@ -271,29 +329,36 @@ int run_phase1(const u32 *rp, const u32 *ci, u32 n, u64 m, const u64 *vptr, u32 
     u64 *outptr = at<u64>(ws, L.outptr), *triptr = at<u64>(ws, L.triptr),
         *bsum = at<u64>(ws, L.bsum);
 
-    HCHK(hipMemsetAsync(st, 0, sizeof(DevState), s));
+    int rc = zero_u64(st, sizeof(DevState) / 8, s);
+    if (rc) return rc;
     k_check_rowptr<<<grid_for(n, WG), WG, 0, s>>>(rp, n, M2, st);
     HCHK(hipGetLastError());
-    int rc = read_state(st, hs, s);
-    if (rc) return rc;
-    if (hs->err) return err_to_status(hs->err);
+    if (!cap) {
+        rc = read_state(st, hs, s);
+        if (rc) return rc;
+        if (hs->err) return err_to_status(hs->err);
+    }
     u32 *gbase = nullptr;
     if (vptr) {
         gbase = at<u32>(ws, L.gbase);
         k_batch_index<<<grid_waves(B), WG, 0, s>>>(vptr, B, n, gbase, st);
         HCHK(hipGetLastError());
-        rc = read_state(st, hs, s);
-        if (rc) return rc;
-        if (hs->err) return err_to_status(hs->err);
+        if (!cap) {
+            rc = read_state(st, hs, s);
+            if (rc) return rc;
+            if (hs->err) return err_to_status(hs->err);
+        }
     }
     if (n) {
         k_src_deg<<<grid_waves(n), WG, 0, s>>>(rp, n, src, deg);
         k_rev<<<grid_for(M2, WG), WG, 0, s>>>(rp, ci, src, gbase, n, M2, rev, st);
         HCHK(hipGetLastError());
     }
-    rc = read_state(st, hs, s);
-    if (rc) return rc;
-    if (hs->err) return err_to_status(hs->err);
+    if (!cap) {
+        rc = read_state(st, hs, s);
+        if (rc) return rc;
+        if (hs->err) return err_to_status(hs->err);
+    }
     tm.mark("validate");
     if (n == 0) return ORB_OK;
 
@@ -301,15 +366,23 @@ int run_phase1(const u32 *rp, const u32 *ci, u32 n, u64 m, const u64 *vptr, u32 
     k_peel_init<<<grid_for(n, WG), WG, 0, s>>>(deg, n, pdeg, rnd, st);
     HCHK(hipGetLastError());
     const unsigned gs = grid_for((u64)n, WG);
+    const int gsz = group_size(n, m);
     for (int it = 0;; it++) {
         for (int k = 0; k < 32; k++) {
-            k_peel_step<<<gs, WG, 0, s>>>(rp, ci, n, pdeg, rnd, front, st);
+            WITH_GROUP(gsz, k_peel_step<GG><<<gs, WG, 0, s>>>(rp, ci, n, pdeg, rnd, front, st));
             k_peel_advance<<<1, 64, 0, s>>>(st);
         }
         HCHK(hipGetLastError());
+        if (cap) {
+            if (it + 1 >= pl->peel_groups) break;
+            continue;
+        }
         rc = read_state(st, hs, s);
         if (rc) return rc;
-        if (hs->alive == 0) break;
+        if (hs->alive == 0) {
+            if (pl) pl->peel_groups = it + 1;
+            break;
+        }
         if (it > (int)(4u * (u64)n / 32u + 1000000)) return ORB_E_INTERNAL;
     }
     k_rank_key<<<grid_for(n, WG), WG, 0, s>>>(rnd, n, key);
@@ -323,11 +396,23 @@ int run_phase1(const u32 *rp, const u32 *ci, u32 n, u64 m, const u64 *vptr, u32 
         k_tri_count<<<grid_for(m, WG), WG, 0, s>>>(src, outptr, outnbr, outslot, m, tcnt);
         rc = scan<u32>(tcnt, m, triptr, bsum, st, s);
         if (rc) return rc;
+        k_save_ntri<<<1, 64, 0, s>>>(st);
     }
     HCHK(hipGetLastError());
-    rc = read_state(st, hs, s);
-    if (rc) return rc;
-    hs->ntri = m ? hs->scan_total : 0;
+    if (cap) {
+        hs->ntri = pl->ntri;
+        hs->maxlevel = pl->maxlevel;
+        hs->gmax = pl->gmax;
+    } else {
+        rc = read_state(st, hs, s);
+        if (rc) return rc;
+        hs->ntri = m ? hs->scan_total : 0;
+        if (pl) {
+            pl->ntri = hs->ntri;
+            pl->maxlevel = hs->maxlevel;
+            pl->gmax = hs->gmax;
+        }
+    }
     tm.mark("orient");
     return ORB_OK;
 }
@@ -335,13 +420,15 @@ int run_phase1(const u32 *rp, const u32 *ci, u32 n, u64 m, const u64 *vptr, u32 
 int count_impl(const u32 *rp, const u32 *ci, u32 n, u64 m, const u64 *vptr, u32 B, int k_max,
                u64 *counts, void *ws,
                u64 ws_bytes, u64 *ws_required, hipStream_t s, const orb_opts *opts,
-               bool query_only) {
+               bool query_only, Plan *pl = nullptr) {
+    const bool cap = pl && pl->capture;
     const u32 flags = opts ? opts->flags : 0u;
     const int K = orbit_num_orbits(k_max);
     if (!K) return ORB_E_INVALID_ARG;
     if (flags & ~(ORB_NONINDUCED | ORB_TIMING)) return ORB_E_INVALID_ARG;
     const u32 sched = opts ? opts->schedule : ORB_SCHED_ID;
-    if (sched > ORB_SCHED_MLP || (opts && opts->reserved)) return ORB_E_INVALID_ARG;
+    if (sched > ORB_SCHED_MLP || (opts && opts->groups > ORB_GROUPS_WAVE))
+        return ORB_E_INVALID_ARG;
     if (sched == ORB_SCHED_MLP && !opts->mlp_weights) return ORB_E_INVALID_ARG;
     if (2 * m >= (1ull << 32)) return ORB_E_INVALID_ARG;
     if (!rp || (m && !ci) || (!counts && !query_only && n)) return ORB_E_INVALID_ARG;
@@ -351,16 +438,23 @@ int count_impl(const u32 *rp, const u32 *ci, u32 n, u64 m, const u64 *vptr, u32 
         if (ws_required) *ws_required = L.p1_end;
         return ORB_E_WORKSPACE;
     }
-    Timer tm((flags & ORB_TIMING) && !query_only, s);
+    Timer tm((flags & ORB_TIMING) && !query_only && !cap, s);
     DevState hs;
     memset(&hs, 0, sizeof hs);
-    int rc = run_phase1(rp, ci, n, m, vptr, B, ws, L, s, &hs, tm);
+    int rc = run_phase1(rp, ci, n, m, vptr, B, ws, L, s, &hs, tm, pl);
     if (rc) return rc;
     const u64 ntri = hs.ntri;
     const u32 dmax = hs.maxlevel + 1;
     const bool ni_in_out = (K == ORB_NORB);
     const u32 mapn = vptr ? (hs.gmax ? hs.gmax : 1) : n;
-    layout_phase2(L, n, mapn, m, ntri, dmax, k_max, ni_in_out, opts ? opts->num_wg : 0);
+    // per-source execution groups: a wave per source for small maps (many
+    // light sources), the whole workgroup per source otherwise
+    const u32 greq = opts ? opts->groups : ORB_GROUPS_AUTO;
+    const bool wave_groups =
+        greq == ORB_GROUPS_WAVE ||
+        (greq == ORB_GROUPS_AUTO && mapn <= kWaveGroupMaxMap && dmax <= kWaveGroupMaxOut);
+    layout_phase2(L, n, mapn, m, ntri, dmax, k_max, ni_in_out, opts ? opts->num_wg : 0,
+                  wave_groups ? WAVES_PER_WG : 1);
     if (ws_required) *ws_required = L.total;
     if (query_only) return ORB_OK;
     if (L.total > ws_bytes) return ORB_E_WORKSPACE;
@@ -387,11 +481,25 @@ int count_impl(const u32 *rp, const u32 *ci, u32 n, u64 m, const u64 *vptr, u32 
     u64 *ni = ni_in_out ? counts : at<u64>(ws, L.ni);
     unsigned char *scratch = at<unsigned char>(ws, L.scratch);
     const u32 *gbase = vptr ? at<u32>(ws, L.gbase) : nullptr;
+    // LDS capacities: clique bit rows up to the largest out-degree, wheel
+    // maps up to the largest map; the 5-cycle kernel runs at most 256
+    // workgroups when its maps are large (measured faster on big graphs)
+    // (out-degrees above the LDS capacity use bit rows in global scratch;
+    // the capacity keeps every group's rows of a workgroup within 64 KB)
+    u32 clq_d = dmax < CLQ_LDS_D ? dmax : CLQ_LDS_D;
+    while (clq_d > 1 && 8ull * L.per_wg * clique_lds_words(clq_d) > kMaxDynLds) clq_d--;
+    const size_t clq_lds = 8ull * L.per_wg * clique_lds_words(clq_d);
+    const u32 pair_kl = ((mapn < PAIR_KMAP_LDS ? mapn : PAIR_KMAP_LDS) + 1) & ~1u;
+    const size_t pair_lds = (size_t)WAVES_PER_WG * pair_kl * 6;
+    const u32 c5_wg = (mapn > 65536 && L.nwg > 256) ? 256 : L.nwg;
+    const u32 grp = L.nwg * L.per_wg, grp5 = c5_wg * L.per_wg;  // scratch rows in use
 
     // zero the accumulators (the contiguous phase-2 region up to ni) and
     // the per-source scratch
-    HCHK(hipMemsetAsync((char *)ws + L.T.off, 0, L.scratch.off - L.T.off, s));
-    HCHK(hipMemsetAsync(ni, 0, 8ull * ORB_NORB * n, s));
+    rc = zero_u64((char *)ws + L.T.off, (L.scratch.off - L.T.off) / 8, s);
+    if (rc) return rc;
+    rc = zero_u64(ni, (u64)ORB_NORB * n, s);
+    if (rc) return rc;
     tm.mark("zero");
 
     // schedule of the per-source kernels
@@ -409,7 +517,8 @@ int count_impl(const u32 *rp, const u32 *ci, u32 n, u64 m, const u64 *vptr, u32 
         }
         u32 *sbin = at<u32>(ws, L.sbin), *shist = at<u32>(ws, L.shist);
         u32 *ord = at<u32>(ws, L.order);
-        HCHK(hipMemsetAsync(shist, 0, 4ull * SCHED_BINS, s));
+        rc = zero_u64(shist, SCHED_BINS / 2, s);
+        if (rc) return rc;
         k_sched_bins<<<grid_for(n, WG), WG, 0, s>>>(feat, pred, n, sbin, shist);
         k_sched_offsets<<<1, 64, 0, s>>>(shist);
         k_sched_scatter<<<grid_for(n, WG), WG, 0, s>>>(sbin, n, shist, ord);
@@ -417,7 +526,10 @@ int count_impl(const u32 *rp, const u32 *ci, u32 n, u64 m, const u64 *vptr, u32 
         order = ord;
     }
     u64 *steps_out = opts ? (u64 *)opts->steps_out : nullptr;
-    if (steps_out) HCHK(hipMemsetAsync(steps_out, 0, 8ull * n, s));
+    if (steps_out) {
+        rc = zero_u64(steps_out, n, s);
+        if (rc) return rc;
+    }
     tm.mark("schedule");
 
     if (ntri) {
@@ -448,66 +560,77 @@ int count_impl(const u32 *rp, const u32 *ci, u32 n, u64 m, const u64 *vptr, u32 
         }
     }
     tm.mark("tri_lists");
-    k_vert0<<<grid_waves(n), WG, 0, s>>>(rp, ci, deg, T, n, Tv, N1);
+    const int gsz = group_size(n, m);
+    WITH_GROUP(gsz, k_vert0<GG><<<grid_for((u64)n * GG, WG), WG, 0, s>>>(rp, ci, deg, T, n, Tv,
+                                                                        N1));
     HCHK(hipGetLastError());
     u32 *work = st->work;
     int wi = 0;
     if (k_max >= 4) {
-        rc = zero_scratch(0, mapn, scratch, L, L.nwg, s);
+        rc = zero_scratch(0, mapn, scratch, L, grp, s);
         if (rc) return rc;
         tm.mark("zero_c4");
-        k_c4<<<L.nwg, WG, 0, s>>>(rp, ci, rev, key, n, scratch, L.stride, work + wi++, order,
-                                  mapn, gbase, C4v, C4e);
+        WITH_GP(wave_groups, k_c4<GPT><<<L.nwg, WG, 0, s>>>(rp, ci, rev, key, n, scratch, L.stride, work + wi++, order,
+                                  mapn, gbase, C4v, C4e));
         HCHK(hipGetLastError());
         tm.mark("c4");
         if (ntri) {
-            k_clique<<<L.nwg, WG, 0, s>>>(1, n, rev, outptr, outnbr, outslot, triptr, tri_c,
-                                          tri_sbc, scratch, L.stride, dmax, work + wi++, order, K4t, K4v, K4e,
-                                          ni, st);
+            WITH_GP(wave_groups, k_clique<GPT><<<L.nwg, WG, clq_lds, s>>>(1, n, rev, outptr, outnbr, outslot, triptr, tri_c,
+                                          tri_sbc, scratch, L.stride, dmax, clq_d, work + wi++, order, K4t, K4v, K4e,
+                                          ni, st));
             HCHK(hipGetLastError());
         }
         tm.mark("cliques");
         if (ntri) {
-            k_trisweep<<<grid_waves(n), WG, 0, s>>>(rp, ci, src, rev, deg, T, tlptr, tl, Tv, N1,
-                                                    E7, E9, C4e, K4e, n, ni);
+            WITH_GROUP(gsz, k_trisweep<GG><<<grid_for((u64)n * GG, WG), WG, 0, s>>>(
+                                rp, ci, src, rev, deg, T, tlptr, tl, Tv, N1, E7, E9, C4e, K4e,
+                                n, ni));
             HCHK(hipGetLastError());
         }
         tm.mark("trisweep");
     }
     if (k_max >= 5) {
         if (ntri) {
-            k_clique<<<L.nwg, WG, 0, s>>>(2, n, rev, outptr, outnbr, outslot, triptr, tri_c,
-                                          tri_sbc, scratch, L.stride, dmax, work + wi++, order, K4t, K4v, K4e,
-                                          ni, st);
+            WITH_GP(wave_groups, k_clique<GPT><<<L.nwg, WG, clq_lds, s>>>(2, n, rev, outptr, outnbr, outslot, triptr, tri_c,
+                                          tri_sbc, scratch, L.stride, dmax, clq_d, work + wi++, order, K4t, K4v, K4e,
+                                          ni, st));
             k_tri_k4terms<<<grid_for(ntri, WG), WG, 0, s>>>(src, ci, T, ntri, tri_c, tri_sab,
                                                             tri_sac, tri_sbc, K4t, ni);
             HCHK(hipGetLastError());
         }
         tm.mark("clique2_k4terms");
-        rc = zero_scratch(1, mapn, scratch, L, L.nwg, s);
+        rc = zero_scratch(1, mapn, scratch, L, grp, s);
         if (rc) return rc;
         tm.mark("zero_pairs");
-        k_pairs<<<L.nwg, WG, 0, s>>>(rp, ci, src, rev, deg, T, tlptr, tl, n, scratch, L.stride,
-                                     work + wi++, order, mapn, gbase, steps_out, Q, ni);
+        WITH_GP(wave_groups, k_pairs<GPT><<<L.nwg, WG, pair_lds, s>>>(rp, ci, src, rev, deg, T, tlptr, tl, n, scratch, L.stride,
+                                     work + wi++, order, mapn, gbase, pair_kl, steps_out, Q, ni));
         HCHK(hipGetLastError());
         tm.mark("pairs");
-        rc = zero_scratch(2, mapn, scratch, L, L.nwg < 256 ? L.nwg : 256, s);
+        rc = zero_scratch(2, mapn, scratch, L, grp5, s);
         if (rc) return rc;
         tm.mark("zero_c5");
-        k_c5<<<L.nwg < 256 ? L.nwg : 256, WG, 0, s>>>(rp, ci, key, outptr, outnbr, outslot, Tin, Tmid, n, scratch,
-                                  L.stride, work + wi++, order, mapn, gbase, steps_out, ni);
+        WITH_GP(wave_groups, k_c5<GPT><<<c5_wg, WG, 0, s>>>(rp, ci, key, outptr, outnbr, outslot, Tin, Tmid, n, scratch,
+                                  L.stride, work + wi++, order, mapn, gbase, steps_out, ni));
         HCHK(hipGetLastError());
         tm.mark("c5");
     }
-    k_vert1<<<grid_waves(n), WG, 0, s>>>(rp, ci, rev, deg, T, Tv, N1, C4v, K4v, C4e, K4e, E9, Q,
-                                         n, ni);
-    if (k_max >= 5) k_vert2<<<grid_waves(n), WG, 0, s>>>(rp, ci, deg, Tv, N1, n, ni);
-    k_transform<<<grid_for(n, WG), WG, 0, s>>>(ni, n, K, (flags & ORB_NONINDUCED) ? 0 : 1, counts);
+    WITH_GROUP(gsz, k_vert1<GG><<<grid_for((u64)n * GG, WG), WG, 0, s>>>(
+                        rp, ci, rev, deg, T, Tv, N1, C4v, K4v, C4e, K4e, E9, Q, n, ni));
+    if (k_max >= 5)
+        WITH_GROUP(gsz, k_vert2<GG><<<grid_for((u64)n * GG, WG), WG, 0, s>>>(rp, ci, deg, Tv, N1,
+                                                                            n, ni));
+    k_transform<<<grid_for(n, XF_ROWS), WAVE, 0, s>>>(ni, n, K, (flags & ORB_NONINDUCED) ? 0 : 1,
+                                                     counts);
     HCHK(hipGetLastError());
     tm.mark("combine");
     if (flags & ORB_TIMING) {
         k_stats<<<grid_for(M2 > n ? M2 : n, WG), WG, 0, s>>>(src, ci, deg, T, n, M2, st);
         HCHK(hipGetLastError());
+    }
+    if (cap) {  // the replay checks that it saw the sizes it was built for
+        k_plan_check<<<1, 64, 0, s>>>(st, pl->ntri, pl->maxlevel, pl->gmax);
+        HCHK(hipGetLastError());
+        return ORB_OK;
     }
     rc = read_state(st, &hs, s);
     if (rc) return rc;
@@ -625,26 +748,112 @@ int orbit_autotune(const uint64_t *vptr, uint32_t num_graphs, const uint32_t *ro
     orb_opts b = o;
     bool warm = false;
     for (int c = 0; c < num_candidates; c++) {
-        for (u32 sc = 0; sc < nsched; sc++) {
-            orb_opts x = o;
-            x.flags = keep_flags | ORB_TIMING;
-            x.num_wg = nwg_candidates[c];
-            x.schedule = sc;
-            int rc = run(x, &ms);
-            if (rc == ORB_E_WORKSPACE) break;  // this candidate does not fit
-            if (rc) return rc;
-            if (!warm) {  // the first run also loads the code and warms caches
-                warm = true;
-                rc = run(x, &ms);
+        for (u32 gr = ORB_GROUPS_WG; gr <= ORB_GROUPS_WAVE; gr++) {
+            for (u32 sc = 0; sc < nsched; sc++) {
+                orb_opts x = o;
+                x.flags = keep_flags | ORB_TIMING;
+                x.num_wg = nwg_candidates[c];
+                x.schedule = sc;
+                x.groups = gr;
+                int rc = run(x, &ms);
+                if (rc == ORB_E_WORKSPACE) break;  // this candidate does not fit
                 if (rc) return rc;
+                if (!warm) {  // the first run also loads the code and warms caches
+                    warm = true;
+                    rc = run(x, &ms);
+                    if (rc) return rc;
+                }
+                if (bms < 0 || ms < bms) { bms = ms; b = x; }
             }
-            if (bms < 0 || ms < bms) { bms = ms; b = x; }
         }
     }
     if (bms < 0) return ORB_E_WORKSPACE;
     b.flags = keep_flags;
     *best = b;
     if (best_ms) *best_ms = bms;
+    return ORB_OK;
+}
+
+struct orb_plan {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    DevState *st = nullptr;  // device state inside the plan's workspace
+};
+
+int orbit_plan_create(const uint64_t *vptr, uint32_t num_graphs, const uint32_t *row_ptr,
+                      const uint32_t *col_idx, uint32_t n, uint64_t m, int k_max,
+                      uint64_t *counts, void *workspace, uint64_t ws_bytes, void *stream,
+                      const orb_opts *opts, orb_plan **plan) {
+    if (!plan) return ORB_E_INVALID_ARG;
+    *plan = nullptr;
+    orb_opts o;
+    memset(&o, 0, sizeof o);
+    if (opts) o = *opts;
+    o.flags &= ~ORB_TIMING;
+    o.features_out = nullptr;
+    o.steps_out = nullptr;
+    hipStream_t s = (hipStream_t)stream;
+    // 1. an ordinary run validates the input and fixes the sizes
+    Plan pl;
+    int rc = count_impl(row_ptr, col_idx, n, m, (const u64 *)vptr, num_graphs, k_max,
+                        (u64 *)counts, workspace, ws_bytes, nullptr, s, &o, false, &pl);
+    if (rc) return rc;
+    if (n == 0) return ORB_E_INVALID_ARG;  // nothing to capture
+    // 2. the same launches, captured on a private stream
+    hipStream_t cs = nullptr;
+    HCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipStreamDestroy(cs);
+        return ORB_E_DEVICE;
+    }
+    pl.capture = true;
+    rc = count_impl(row_ptr, col_idx, n, m, (const u64 *)vptr, num_graphs, k_max,
+                    (u64 *)counts, workspace, ws_bytes, nullptr, cs, &o, false, &pl);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(cs, &g);
+    (void)hipStreamDestroy(cs);
+    if (rc || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc ? rc : ORB_E_DEVICE;
+    }
+    hipGraphExec_t ex = nullptr;
+    if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return ORB_E_DEVICE;
+    }
+    orb_plan *p = new (std::nothrow) orb_plan;
+    if (!p) {
+        (void)hipGraphExecDestroy(ex);
+        (void)hipGraphDestroy(g);
+        return ORB_E_DEVICE;
+    }
+    Layout L;
+    layout_phase1(L, n, m);
+    p->graph = g;
+    p->exec = ex;
+    p->st = at<DevState>(workspace, L.state);
+    *plan = p;
+    return ORB_OK;
+}
+
+int orbit_plan_launch(orb_plan *plan, void *stream) {
+    if (!plan) return ORB_E_INVALID_ARG;
+    return hipGraphLaunch(plan->exec, (hipStream_t)stream) == hipSuccess ? ORB_OK : ORB_E_DEVICE;
+}
+
+int orbit_plan_status(orb_plan *plan, void *stream) {
+    if (!plan) return ORB_E_INVALID_ARG;
+    DevState h;
+    int rc = read_state(plan->st, &h, (hipStream_t)stream);
+    if (rc) return rc;
+    return h.err ? err_to_status(h.err) : ORB_OK;
+}
+
+int orbit_plan_destroy(orb_plan *plan) {
+    if (!plan) return ORB_OK;
+    if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+    if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    delete plan;
     return ORB_OK;
 }
 

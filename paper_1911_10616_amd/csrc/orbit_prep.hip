@@ -77,6 +77,9 @@ __global__ void k_peel_init(const u32 *deg, u32 n, int *pdeg, u32 *rnd, DevState
     }
 }
 
+// The frontier is processed by groups of G lanes per vertex (G from the
+// mean degree).
+template <int G>
 __global__ void k_peel_step(const u32 *rp, const u32 *ci, u32 n, int *pdeg, u32 *rnd,
                             u32 *front, DevState *st) {
     const u32 cur = st->cur, nxt = cur ^ 1u;
@@ -97,9 +100,9 @@ __global__ void k_peel_step(const u32 *rp, const u32 *ci, u32 n, int *pdeg, u32 
             }
         }
     } else {
-        for (u64 i = GWAVE; i < fs; i += NWAVES) {
+        for (u64 i = GTID / G; i < fs; i += GSTRIDE / G) {
             u32 u = front[(u64)cur * n + i];
-            for (u32 s = rp[u] + lane_id(); s < rp[u + 1]; s += WAVE) {
+            for (u32 s = rp[u] + (threadIdx.x & (G - 1)); s < rp[u + 1]; s += G) {
                 u32 w = ci[s];
                 if (rnd[w] != UNSET) continue;
                 int old = atomicSub(&pdeg[w], 1);
@@ -266,3 +269,26 @@ __global__ void k_fill_u64(u64 *p, u64 len, u64 v) {
 __global__ void k_fill_u32(u32 *p, u64 len, u32 v) {
     for (u64 i = GTID; i < len; i += GSTRIDE) p[i] = v;
 }
+
+// Zero `rows` rows of `width` u64 words, `pitch` bytes apart (the
+// per-source scratch ranges; a kernel rather than a 2-D memset so that the
+// whole count can be captured into a graph).
+__global__ void k_zero_rows(unsigned char *base, u64 pitch, u64 width, u64 rows) {
+    for (u64 i = GTID; i < width * rows; i += GSTRIDE) {
+        const u64 r = i / width, w = i - r * width;
+        ((u64 *)(base + r * pitch))[w] = 0;
+    }
+}
+
+// Plans: the triangle count as left by the last scan of phase 1, and the
+// check that a replayed graph saw the same sizes as the run it was built
+// from (same peel completion, triangle count, degeneracy, largest graph).
+__global__ void k_save_ntri(DevState *st) {
+    if (GTID == 0) st->ntri = st->scan_total;
+}
+__global__ void k_plan_check(DevState *st, u64 ntri, u32 maxlevel, u32 gmax) {
+    if (GTID == 0 && (st->alive != 0 || st->ntri != ntri || st->maxlevel != maxlevel ||
+                      st->gmax != gmax))
+        atomicOr(&st->err, ERRB_INTERNAL);
+}
+

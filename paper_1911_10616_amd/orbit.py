@@ -18,12 +18,14 @@ ORB_NONINDUCED = 0x1
 ORB_TIMING = 0x2
 SCHED_ID, SCHED_STATIC, SCHED_MLP = 0, 1, 2
 SCHEDULES = {"id": SCHED_ID, "static": SCHED_STATIC, "mlp": SCHED_MLP}
+GROUPS = {"auto": 0, "wg": 1, "wave": 2}
 MLP_PARAMS = 1217
 
 EXPORTS = ("orbit_num_orbits", "orbit_count", "orbit_workspace_query", "orbit_count_ex",
            "orbit_strerror", "orbit_last_phase_times", "orbit_last_stats", "orbit_mlp_init",
            "orbit_mlp_predict", "orbit_mlp_grad", "orbit_mlp_train", "orbit_count_batched",
-           "orbit_workspace_query_batched", "orbit_autotune")
+           "orbit_workspace_query_batched", "orbit_autotune", "orbit_plan_create",
+           "orbit_plan_launch", "orbit_plan_status", "orbit_plan_destroy")
 
 
 class OrbError(RuntimeError):
@@ -34,7 +36,7 @@ class OrbError(RuntimeError):
 
 class _Opts(ctypes.Structure):
     _fields_ = [("flags", ctypes.c_uint32), ("num_wg", ctypes.c_uint32),
-                ("schedule", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("schedule", ctypes.c_uint32), ("groups", ctypes.c_uint32),
                 ("mlp_weights", ctypes.c_void_p), ("features_out", ctypes.c_void_p),
                 ("steps_out", ctypes.c_void_p)]
 
@@ -82,6 +84,14 @@ def _load():
                                    ctypes.POINTER(_Opts), ctypes.POINTER(u32), ctypes.c_int,
                                    ctypes.POINTER(_Opts), ctypes.POINTER(ctypes.c_float)]
     lib.orbit_autotune.restype = ctypes.c_int
+    lib.orbit_plan_create.argtypes = [vp, u32, vp, vp, u32, u64, ctypes.c_int, vp, vp, u64, vp,
+                                      ctypes.POINTER(_Opts), ctypes.POINTER(vp)]
+    lib.orbit_plan_create.restype = ctypes.c_int
+    for f in (lib.orbit_plan_launch, lib.orbit_plan_status):
+        f.argtypes = [vp, vp]
+        f.restype = ctypes.c_int
+    lib.orbit_plan_destroy.argtypes = [vp]
+    lib.orbit_plan_destroy.restype = ctypes.c_int
     return lib
 
 
@@ -116,17 +126,19 @@ def _ptr(t):
 
 
 def _opts(noninduced=False, timing=False, num_wg=0, schedule=SCHED_ID, mlp_weights=None,
-          features_out=None, steps_out=None):
+          features_out=None, steps_out=None, groups=0):
     f = (ORB_NONINDUCED if noninduced else 0) | (ORB_TIMING if timing else 0)
-    return _Opts(f, num_wg, schedule, 0, _ptr(mlp_weights), _ptr(features_out), _ptr(steps_out))
+    g = GROUPS[groups] if isinstance(groups, str) else int(groups)
+    return _Opts(f, num_wg, schedule, g, _ptr(mlp_weights), _ptr(features_out), _ptr(steps_out))
 
 
-def workspace_bytes(row_ptr, col_idx, k_max=5, noninduced=False, num_wg=0, stream=None) -> int:
+def workspace_bytes(row_ptr, col_idx, k_max=5, noninduced=False, num_wg=0, stream=None,
+                    groups="auto") -> int:
     rp, ci = _dev_csr(row_ptr, col_idx)
     n = rp.numel() - 1
     m = int(rp[-1].item()) // 2 if n >= 0 else 0
     out = ctypes.c_uint64(0)
-    o = _opts(noninduced, False, num_wg)
+    o = _opts(noninduced, False, num_wg, groups=groups)
     st = _lib.orbit_workspace_query(ctypes.c_void_p(rp.data_ptr()), ctypes.c_void_p(ci.data_ptr()),
                                     n, m, k_max, _stream_ptr(stream), ctypes.byref(o),
                                     ctypes.byref(out))
@@ -144,7 +156,8 @@ class Counter:
     (use ``.cpu().numpy().view(np.uint64)``)."""
 
     def __init__(self, row_ptr, col_idx, k_max=5, noninduced=False, num_wg=0, stream=None,
-                 schedule="id", mlp_weights=None, features_out=None, steps_out=None):
+                 schedule="id", mlp_weights=None, features_out=None, steps_out=None,
+                 groups="auto"):
         """schedule: "id", "static" or "mlp" (source order of the per-source
         kernels; needs mlp_weights, a float32 device tensor of MLP_PARAMS
         values, for "mlp").  features_out (float32 [n, 3]) and steps_out
@@ -160,12 +173,13 @@ class Counter:
             raise OrbError(-1, "k_max")
         sched = SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule)
         extra = dict(schedule=sched, mlp_weights=mlp_weights, features_out=features_out,
-                     steps_out=steps_out)
+                     steps_out=steps_out, groups=groups)
         self._keep = (mlp_weights, features_out, steps_out)
         self.opts = _opts(noninduced, False, num_wg, **extra)
         self.topts = _opts(noninduced, True, num_wg, **extra)
         self.stream = stream
-        self.ws_bytes = workspace_bytes(self.rp, self.ci, k_max, noninduced, num_wg, stream)
+        self.ws_bytes = workspace_bytes(self.rp, self.ci, k_max, noninduced, num_wg, stream,
+                                        groups=groups)
         self.ws = torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8, device=self.rp.device)
         self.out = torch.empty((max(self.n, 1), self.K), dtype=torch.int64, device=self.rp.device)
 
@@ -182,9 +196,9 @@ class Counter:
         return self.out[: self.n]
 
 
-def count(row_ptr, col_idx, k_max=5, noninduced=False, num_wg=0) -> np.ndarray:
+def count(row_ptr, col_idx, k_max=5, noninduced=False, num_wg=0, groups="auto") -> np.ndarray:
     """uint64[n, K] orbit counts (induced unless noninduced=True)."""
-    c = Counter(row_ptr, col_idx, k_max, noninduced, num_wg)
+    c = Counter(row_ptr, col_idx, k_max, noninduced, num_wg, groups=groups)
     return c.run().cpu().numpy().view(np.uint64)
 
 
@@ -234,7 +248,7 @@ class BatchCounter:
     result are graph g's counts.  Options as for Counter."""
 
     def __init__(self, vptr, row_ptr, col_idx, k_max=5, noninduced=False, num_wg=0,
-                 stream=None, schedule="id", mlp_weights=None):
+                 stream=None, schedule="id", mlp_weights=None, groups="auto"):
         import torch
         self.vptr = _dev_u64(vptr)
         self.B = self.vptr.numel() - 1
@@ -246,19 +260,19 @@ class BatchCounter:
         self.stream = stream
         self.noninduced = noninduced
         self._w = mlp_weights
-        self.set_options(num_wg, schedule)
+        self.set_options(num_wg, schedule, groups)
         self.out = torch.empty((max(self.n, 1), self.K), dtype=torch.int64, device=self.rp.device)
 
     def _args(self):
         return (ctypes.c_void_p(self.vptr.data_ptr()), self.B, ctypes.c_void_p(self.rp.data_ptr()),
                 ctypes.c_void_p(self.ci.data_ptr()), self.n, self.m, self.k_max)
 
-    def set_options(self, num_wg, schedule):
+    def set_options(self, num_wg, schedule, groups="auto"):
         """(Re)size the workspace for these options."""
         import torch
         sched = SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule)
-        self.opts = _opts(self.noninduced, False, num_wg, sched, self._w)
-        self.topts = _opts(self.noninduced, True, num_wg, sched, self._w)
+        self.opts = _opts(self.noninduced, False, num_wg, sched, self._w, groups=groups)
+        self.topts = _opts(self.noninduced, True, num_wg, sched, self._w, groups=groups)
         need = ctypes.c_uint64(0)
         _check(_lib.orbit_workspace_query_batched(*self._args(), _stream_ptr(self.stream),
                                                   ctypes.byref(self.opts), ctypes.byref(need)),
@@ -276,11 +290,12 @@ class BatchCounter:
         return self.out[: self.n]
 
     def autotune(self, nwg_candidates=(256, 512, 1024, 2048, 4096)):
-        """Pick num_wg and schedule by timing each candidate (orbit_autotune);
-        keeps the choice and returns (num_wg, schedule, gpu_ms)."""
+        """Pick num_wg, schedule and execution groups by timing each candidate
+        (orbit_autotune); keeps the choice and returns (num_wg, schedule,
+        groups, gpu_ms)."""
         import torch
         big = max(nwg_candidates)
-        self.set_options(big, self.opts.schedule)
+        self.set_options(big, self.opts.schedule, "wave")
         cand = (ctypes.c_uint32 * len(nwg_candidates))(*nwg_candidates)
         best = _Opts()
         ms = ctypes.c_float(0)
@@ -290,14 +305,55 @@ class BatchCounter:
                                    _stream_ptr(self.stream), ctypes.byref(base), cand,
                                    len(nwg_candidates), ctypes.byref(best), ctypes.byref(ms)),
                "orbit_autotune")
-        self.set_options(best.num_wg, best.schedule)
-        return int(best.num_wg), int(best.schedule), float(ms.value)
+        self.set_options(best.num_wg, best.schedule, best.groups)
+        return int(best.num_wg), int(best.schedule), int(best.groups), float(ms.value)
+
+
+class Plan:
+    """The whole count of a Counter or BatchCounter captured as one HIP
+    graph (orbit_plan_create); launch() replays it into the counter's
+    output buffer without any host synchronisation.  The input buffers must
+    stay unchanged."""
+
+    def __init__(self, counter):
+        self.c = counter
+        vptr = getattr(counter, "vptr", None)
+        B = getattr(counter, "B", 0)
+        h = ctypes.c_void_p(0)
+        _check(_lib.orbit_plan_create(
+            ctypes.c_void_p(vptr.data_ptr()) if vptr is not None else None, B,
+            ctypes.c_void_p(counter.rp.data_ptr()), ctypes.c_void_p(counter.ci.data_ptr()),
+            counter.n, counter.m, counter.k_max, ctypes.c_void_p(counter.out.data_ptr()),
+            ctypes.c_void_p(counter.ws.data_ptr()), counter.ws_bytes,
+            _stream_ptr(counter.stream), ctypes.byref(counter.opts), ctypes.byref(h)),
+            "orbit_plan_create")
+        self.h = h
+
+    def launch(self):
+        _check(_lib.orbit_plan_launch(self.h, _stream_ptr(self.c.stream)), "orbit_plan_launch")
+        return self.c.out[: self.c.n]
+
+    def status(self):
+        """Waits for the stream; raises if the last replay reported an error."""
+        _check(_lib.orbit_plan_status(self.h, _stream_ptr(self.c.stream)), "orbit_plan_status")
+
+    def close(self):
+        if self.h:
+            _lib.orbit_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def count_batched(vptr, row_ptr, col_idx, k_max=5, noninduced=False, num_wg=0,
-                  schedule="id") -> np.ndarray:
+                  schedule="id", groups="auto") -> np.ndarray:
     """uint64[n, K]: per-graph counts of a batch, concatenated by graph."""
-    c = BatchCounter(vptr, row_ptr, col_idx, k_max, noninduced, num_wg, schedule=schedule)
+    c = BatchCounter(vptr, row_ptr, col_idx, k_max, noninduced, num_wg, schedule=schedule,
+                     groups=groups)
     return c.run().cpu().numpy().view(np.uint64)
 
 

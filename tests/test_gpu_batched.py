@@ -33,11 +33,12 @@ def _graph(vptr, rp, ci, g):
     return (rp[a:b + 1] - rp[a]).astype(np.uint32), (ci[rp[a]:rp[b]] - a).astype(np.uint32)
 
 
-@pytest.mark.parametrize("schedule", ["id", "static"])
-def test_small_batch_per_graph_oracle(orbit, schedule):
+@pytest.mark.parametrize("schedule,groups", [("id", "wave"), ("static", "wave"), ("id", "wg"),
+                                             ("static", "wg")])
+def test_small_batch_per_graph_oracle(orbit, schedule, groups):
     vptr, rp, ci = gg.batch_small(60, 101, nmin=5, nmax=40)
-    _say("batch of 60, n", len(rp) - 1, "schedule", schedule)
-    got = orbit.count_batched(vptr, rp, ci, 5, schedule=schedule)
+    _say("batch of 60, n", len(rp) - 1, "schedule", schedule, "groups", groups)
+    got = orbit.count_batched(vptr, rp, ci, 5, schedule=schedule, groups=groups)
     for g in range(60):
         a, b = int(vptr[g]), int(vptr[g + 1])
         np.testing.assert_array_equal(got[a:b], oracle.induced_counts(*_graph(vptr, rp, ci, g)),
@@ -129,7 +130,34 @@ def test_autotune_keeps_counts(orbit):
     vptr, rp, ci = gg.batch_small(400, 106)
     c = orbit.BatchCounter(vptr, rp, ci, 5)
     ref = c.run().cpu().numpy().copy()
-    nwg, sched, ms = c.autotune((128, 512, 2048))
-    _say("autotune", nwg, sched, ms)
-    assert nwg in (128, 512, 2048) and sched in (0, 1) and ms > 0
+    nwg, sched, groups, ms = c.autotune((128, 512, 2048))
+    _say("autotune", nwg, sched, groups, ms)
+    assert nwg in (128, 512, 2048) and sched in (0, 1) and groups in (1, 2) and ms > 0
+    np.testing.assert_array_equal(c.run().cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("batched", [True, False])
+def test_plan_replays_match_eager(orbit, batched):
+    """A captured plan, replayed several times with ordinary work and
+    synchronisations in between, gives the eager counts every time."""
+    import torch
+    if batched:
+        vptr, rp, ci = gg.batch_small(300, 107)
+        c = orbit.BatchCounter(vptr, rp, ci, 5)
+    else:
+        rp, ci = gg.chung_lu(3000, 10.0, 2.1, 300.0, 15000, 108)
+        c = orbit.Counter(rp, ci, 5, schedule="static")
+    ref = c.run().cpu().numpy().copy()
+    plan = orbit.Plan(c)
+    for rep in range(4):
+        c.out.fill_(-1)
+        torch.cuda.synchronize()
+        got = plan.launch()
+        plan.status()
+        np.testing.assert_array_equal(got.cpu().numpy(), ref, err_msg=f"replay {rep}")
+        # ordinary work between replays
+        x = torch.arange(1 << 20, device="cuda").sum()
+        torch.cuda.synchronize()
+        assert int(x) == (1 << 20) * ((1 << 20) - 1) // 2
+    plan.close()
     np.testing.assert_array_equal(c.run().cpu().numpy(), ref)

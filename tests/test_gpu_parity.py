@@ -222,3 +222,16 @@ def test_argument_errors(orbit):
     st, _ = orbit.raw_count_ex(drp.data_ptr(), dci.data_ptr(), 6, 6, 5, out.data_ptr(),
                                ws.data_ptr(), ws.numel(), flags=0x80)
     assert st == -1  # unknown flag
+
+
+@pytest.mark.parametrize("groups", ["wg", "wave"])
+def test_execution_groups(orbit, groups):
+    """A workgroup per source and a wave per source give the same counts."""
+    graphs = [gg.erdos_renyi(40, 0.3, 11), gg.barabasi_albert(150, 3, 12),
+              gg.chung_lu(500, 8.0, 2.1, 80.0, 2000, 13), gg.complete(12), _book(70)]
+    for i, (rp, ci) in enumerate(graphs):
+        _say("groups", groups, "graph", i)
+        np.testing.assert_array_equal(orbit.count(rp, ci, 5, groups=groups),
+                                      oracle.induced_counts(rp, ci, threads=8))
+        np.testing.assert_array_equal(orbit.count(rp, ci, 5, noninduced=True, groups=groups),
+                                      oracle.noninduced_counts(rp, ci, threads=8))

@@ -150,15 +150,16 @@ def test_schedule_argument_errors(orbit):
     ws = torch.empty(orbit.workspace_bytes(rp, ci, 5), dtype=torch.uint8, device="cuda")
     lib = orbit._lib
     w = orbit.mlp_init()
-    for sched, reserved, wp, want in ((3, 0, w.data_ptr(), -1), (2, 0, None, -1),
-                                      (0, 1, None, -1), (2, 0, w.data_ptr(), 0)):
-        o = orbit._Opts(0, 0, sched, reserved, wp, None, None)
+    for sched, groups, wp, want in ((3, 0, w.data_ptr(), -1), (2, 0, None, -1),
+                                    (0, 3, None, -1), (2, 0, w.data_ptr(), 0),
+                                    (1, 1, None, 0), (1, 2, None, 0)):
+        o = orbit._Opts(0, 0, sched, groups, wp, None, None)
         need = ctypes.c_uint64(0)
         st = lib.orbit_count_ex(ctypes.c_void_p(rpd.data_ptr()), ctypes.c_void_p(cid.data_ptr()),
                                 5, 10, 5, ctypes.c_void_p(out.data_ptr()),
                                 ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.byref(need),
                                 None, ctypes.byref(o))
-        assert st == want, (sched, reserved, st)
+        assert st == want, (sched, groups, st)
     assert lib.orbit_mlp_train(None, None, 0, None, None, 1, 1, ctypes.c_float(1e-3), 0, None) == -1
 
 
