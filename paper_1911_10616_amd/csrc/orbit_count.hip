@@ -900,6 +900,47 @@ __device__ inline bool out_adjacent(u32 k, u32 i, const u64 *out_ptr, const u32 
     return bfind(out_nbr + b, (u32)(out_ptr[k + 1] - b), i) != UNSET;
 }
 
+// Per-wave hash set of N+(k) in LDS (open addressing, keys id + 1, 0 =
+// empty), for the test "k -> i" of every directed 3-path through k; used
+// when d+(k) <= C5_HSET / 2, else a binary search in N+(k).
+#define C5_HSET 1024
+__device__ inline u32 hset_slot(u32 key) { return (key * 2654435761u) >> 22; }
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+__device__ inline bool hset_build(u32 *hs, u32 k, const u64 *out_ptr, const u32 *out_nbr) {
+    const u64 b = out_ptr[k], e = out_ptr[k + 1];
+    if (e - b > C5_HSET / 2) return false;
+    for (u64 q = b + lane_id(); q < e; q += WAVE) {
+        const u32 key = out_nbr[q] + 1;
+        u32 h = hset_slot(key);
+        for (;;) {  // at most half full: a free slot is always found
+            const u32 old = atomicCAS(&hs[h], 0u, key);
+            if (old == 0u || old == key) break;
+            h = (h + 1) & (C5_HSET - 1);
+        }
+    }
+    wave_sync();
+    return true;
+}
+__device__ inline bool hset_has(const u32 *hs, u32 x) {
+    const u32 key = x + 1;
+    u32 h = hset_slot(key);
+    for (;;) {
+        const u32 v = hs[h];
+        if (v == key) return true;
+        if (v == 0u) return false;
+        h = (h + 1) & (C5_HSET - 1);
+    }
+}
+__device__ inline void hset_clear(u32 *hs) {
+    wave_sync();
+    for (u32 i = lane_id(); i < C5_HSET; i += WAVE) hs[i] = 0;
+    wave_sync();
+}
+
 template <class GP>
 __global__ void __launch_bounds__(WG) k_c5(const u32 *rp, const u32 *ci, const u64 *key,
                                           const u64 *out_ptr, const u32 *out_nbr,
@@ -914,6 +955,10 @@ __global__ void __launch_bounds__(WG) k_c5(const u32 *rp, const u32 *ci, const u
     u32 &sh_next = sh_next_[GP::id()];
     __shared__ u64 sh_red[WAVES_PER_WG];
     C5Scratch C = c5_scratch(scratch + GP::global_id() * stride, mapn);
+    __shared__ u32 l_hs[WAVES_PER_WG][C5_HSET];
+    for (u32 i = threadIdx.x; i < WAVES_PER_WG * C5_HSET; i += WG) (&l_hs[0][0])[i] = 0;
+    __syncthreads();
+    u32 *hs = l_hs[wave_in_wg()];
     for (;;) {
         const u32 l = next_source<GP>(work, sh_q, order, n);
         if (l >= n) break;
@@ -941,6 +986,7 @@ __global__ void __launch_bounds__(WG) k_c5(const u32 *rp, const u32 *ci, const u
                 }
                 // w plays k: 3-paths i <- j <- w -> l
                 const u32 k = w;
+                const bool use_hs = hset_build(hs, k, out_ptr, out_nbr);
                 for (u64 qj = out_ptr[k]; qj < out_ptr[k + 1]; qj++) {
                     const u32 j = out_nbr[qj];
                     if (j == l) continue;
@@ -951,10 +997,11 @@ __global__ void __launch_bounds__(WG) k_c5(const u32 *rp, const u32 *ci, const u
                         if (i == l) continue;
                         u64 old = atomicAdd(&C.P[i - vb], 1ull);
                         if (old == 0) C.touched[atomicAdd(&sh_nt, 1u)] = i;
-                        const u64 ik = out_adjacent(k, i, out_ptr, out_nbr) ? 1 : 0;
-                        atomic_add_u64(&C.CI[i - vb], ik + jl);
+                        const bool kin = use_hs ? hset_has(hs, i) : out_adjacent(k, i, out_ptr, out_nbr);
+                        atomic_add_u64(&C.CI[i - vb], (kin ? 1 : 0) + jl);
                     }
                 }
+                if (use_hs) hset_clear(hs);
             }
         });
         GP::sync();
@@ -989,6 +1036,7 @@ __global__ void __launch_bounds__(WG) k_c5(const u32 *rp, const u32 *ci, const u
                 }
                 // 3-paths through k = w: credits of j and k
                 const u32 k = w;
+                const bool use_hs = hset_build(hs, k, out_ptr, out_nbr);
                 u64 acck = 0;
                 for (u64 qj = out_ptr[k]; qj < out_ptr[k + 1]; qj++) {
                     const u32 j = out_nbr[qj];
@@ -998,14 +1046,15 @@ __global__ void __launch_bounds__(WG) k_c5(const u32 *rp, const u32 *ci, const u
                     for (u64 qi = out_ptr[j] + lane_id(); qi < out_ptr[j + 1]; qi += WAVE) {
                         const u32 i = out_nbr[qi];
                         if (i == l) continue;
-                        const u64 ik = out_adjacent(k, i, out_ptr, out_nbr) ? 1 : 0;
-                        accj += (u64)C.Wm[i - vb] - ik - jl;
+                        const bool kin = use_hs ? hset_has(hs, i) : out_adjacent(k, i, out_ptr, out_nbr);
+                        accj += (u64)C.Wm[i - vb] - (kin ? 1 : 0) - jl;
                     }
                     accj = wave_sum_u64(accj);
                     if (lane_id() == 0) atomic_add_u64(&NI(j, 34), accj);
                     acck += accj;
                 }
                 if (lane_id() == 0) atomic_add_u64(&NI(k, 34), acck);
+                if (use_hs) hset_clear(hs);
             }
             accw = wave_sum_u64(accw);
             if (lane_id() == 0) atomic_add_u64(&NI(w, 34), accw);
