@@ -755,22 +755,40 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
             unsigned short *tl_l = l_tk0 + wave_in_wg() * kl;
             TLView tv = tl_view(say, src, ci, rev, T, tl_ptr, tl);
             u32 *ntk = &sh_ntk[wave_in_wg()];
-            for (u32 k = 0; k < tv.len; k++) {
-                const uint2 ez = tv.get(k);  // (slot(a,z), slot(y,z))
-                const TLView tw = tl_view(ez.y, src, ci, rev, T, tl_ptr, tl);
-                // first entry whose third vertex exceeds a
-                u32 lo = 0, hi = tw.len;
-                while (lo < hi) {
-                    const u32 mid = (lo + hi) >> 1;
-                    if (ci[tw.get(mid).x] <= a) lo = mid + 1; else hi = mid;
+            // b > a  <=>  slot(y,b) >= ya, the first slot of N(y) above a
+            const u32 ya = by + lbound(ci + by, dy, a + 1);
+            for (u32 k0 = 0; k0 < tv.len; k0 += WAVE) {
+                // each lane locates the part b > a of one list (y,z) ...
+                const u32 kk = k0 + lane_id();
+                const uint2 *lp = nullptr;
+                u32 lo = 0, len = 0, sw = 0;
+                if (kk < tv.len) {
+                    const uint2 ez = tv.get(kk);  // (slot(a,z), slot(y,z))
+                    const TLView tw = tl_view(ez.y, src, ci, rev, T, tl_ptr, tl);
+                    u32 hi = tw.len;
+                    while (lo < hi) {
+                        const u32 mid = (lo + hi) >> 1;
+                        if (tw.get(mid).x < ya) lo = mid + 1; else hi = mid;
+                    }
+                    lp = tw.p;
+                    len = tw.len;
+                    sw = tw.swap;
                 }
-                for (u32 q = lo + lane_id(); q < tw.len; q += WAVE) {
-                    const u32 pos = tw.get(q).x - by;  // slot(y,b) - rp[y]
-                    nsteps++;
-                    u32 old = atomicAdd(&kc[pos], 1u);
-                    if (old == 0) {
-                        const u32 t = atomicAdd(ntk, 1u);
-                        if (inl) tl_l[t] = (unsigned short)pos; else tkw[t] = pos;
+                // ... then the wave walks those parts one list at a time
+                const u32 cnt = tv.len - k0 < WAVE ? tv.len - k0 : WAVE;
+                for (u32 j = 0; j < cnt; j++) {
+                    const uint2 *pj = (const uint2 *)__shfl((unsigned long long)lp, (int)j, WAVE);
+                    const u32 loj = __shfl(lo, (int)j, WAVE), lenj = __shfl(len, (int)j, WAVE);
+                    const u32 swj = __shfl(sw, (int)j, WAVE);
+                    for (u32 q = loj + lane_id(); q < lenj; q += WAVE) {
+                        const uint2 e = pj[q];
+                        const u32 pos = (swj ? e.y : e.x) - by;  // slot(y,b) - rp[y]
+                        nsteps++;
+                        u32 old = atomicAdd(&kc[pos], 1u);
+                        if (old == 0) {
+                            const u32 t = atomicAdd(ntk, 1u);
+                            if (inl) tl_l[t] = (unsigned short)pos; else tkw[t] = pos;
+                        }
                     }
                 }
             }
