@@ -102,7 +102,12 @@ typedef struct orb_opts {
                                  (log2(1+d+(u)), log2(1+sum_{w in N+(u)} d+(w)), log2(1+d(u)))
                                  under the degeneracy orientation */
     uint64_t *steps_out;      /* device, n uint64, nullable: per-source loop iterations
-                                 of the pair sweep (the cost model's training target) */
+                                 of the pair sweep and the 5-cycle kernel (the cost
+                                 model's training target) */
+    uint64_t *pass_cycles_out; /* device, 4 uint64, nullable (profiling): shader clock
+                                  cycles summed over execution groups in the pair sweep's
+                                  passes: wedges, wheel maps, pair terms, centre terms;
+                                  accumulated (the caller zeroes them) */
 } orb_opts;
 
 /* Number of output columns K for k_max (3, 4 or 5); 0 if k_max is invalid. */

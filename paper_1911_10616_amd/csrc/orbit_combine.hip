@@ -108,7 +108,7 @@ template <int G>
 __global__ void k_vert1(const u32 *rp, const u32 *ci, const u32 *rev, const u32 *deg,
                         const u32 *T, const u64 *Tv, const u64 *N1, const u64 *C4v,
                         const u64 *K4v, const u64 *C4e, const u64 *K4e, const u64 *E9,
-                        const u64 *Q, u32 n, u64 *ni) {
+                        const u64 *Q, const u64 *vacc, const u64 *cacc, u32 n, u64 *ni) {
     GROUP_LOOP(G, u, n) {
         const u64 du = u < n ? deg[u] : 0;
         u64 s4 = 0, n6 = 0, n9 = 0, n10 = 0, n13 = 0, s28 = 0, s31 = 0, n22 = 0, s37 = 0,
@@ -181,6 +181,17 @@ __global__ void k_vert1(const u32 *rp, const u32 *ci, const u32 *rev, const u32 
             NI(u, 60) = s60;
             NI(u, 67) = n67;
             NI(u, 69) = (qlo >> 1) | (qhi << 63);
+            // pair sweep and 5-cycle results (zero when those kernels did not run)
+            const u64 *va = vacc + u * 8;
+            NI(u, 36) = va[0];
+            NI(u, 50) = va[1];
+            NI(u, 51) = va[2];
+            NI(u, 63) = va[3];
+            NI(u, 68) = va[4];
+            NI(u, 64) = va[5];
+            NI(u, 49) = va[6];
+            NI(u, 62) = va[7];
+            NI(u, 34) = cacc[u];
         }
     }
 }

@@ -653,26 +653,58 @@ __global__ void k_tri_k4terms(const u32 *src, const u32 *ci, const u32 *T, u64 n
 //     the sum of Q over the arcs into y).
 // The remaining subtractions (36: -N13, 51: -2 N12, 62: -N13) happen in the
 // per-vertex combine.
+// Profiling of the pair sweep: pass_cycles[k-1] accumulates the shader
+// clock cycles that execution groups spend in pass k (1 wedges, 2 wheel
+// maps, 3 pair terms, 4 centre terms); the group synchronises at each
+// boundary so that the pass is complete.
+template <class GP>
+__device__ inline void pass_mark_g(u64 *pc, int k, u64 &t) {
+    GP::sync();
+    if (GP::rank() == 0) {
+        const u64 now = clock64();
+        if (k > 0) atomicAdd(&pc[k - 1], now - t);
+        t = now;
+    }
+}
+#define pass_mark(pc, k, t) pass_mark_g<GP>(pc, k, t)
+
 // wheel maps of up to this many positions live in LDS (per wave)
 #ifndef PAIR_KMAP_LDS
 #define PAIR_KMAP_LDS 2048
 #endif
+// The pair sweep's per-vertex results go to a compact accumulator of eight
+// words per vertex (one cache line; the combine copies them into the orbit
+// columns) rather than into five lines of the 73-word rows.
+#define VA_36 0
+#define VA_50 1
+#define VA_51 2
+#define VA_63 3
+#define VA_68 4
+#define VA_64 5
+#define VA_49 6
+#define VA_62 7
+#define VACC(u, k) vacc[(u64)(u) * 8 + (k)]
+
+// Per-vertex record of the pair (a, b): everything the passes touch for b
+// lies in one 32-byte sector, so a wedge's three updates, the centre pass's
+// two reads and the pair terms' five reads cost one sector each.
+struct PairRec {
+    u32 s;    // |N(a) & N(b)|
+    u32 adj;  // b ~ a
+    u64 ta;   // sum over y in S of T(a,y)
+    u64 tb;   // sum over y in S of T(y,b)
+    u64 e2;   // 2 |E(S)|
+};
 struct PairScratch {
-    u32 *S;
-    u64 *E, *TA, *TB;
-    unsigned char *mark;
+    PairRec *R;       // n records
     u32 *touched;
     u32 *K;   // WAVES_PER_WG x n
     u32 *tk;  // WAVES_PER_WG x n
 };
 __device__ inline PairScratch pair_scratch(unsigned char *base, u32 n) {
     PairScratch p;
-    p.S = (u32 *)base;
-    p.E = (u64 *)align256((unsigned char *)(p.S + n));
-    p.TA = (u64 *)align256((unsigned char *)(p.E + n));
-    p.TB = (u64 *)align256((unsigned char *)(p.TA + n));
-    p.mark = align256((unsigned char *)(p.TB + n));
-    p.touched = (u32 *)align256(p.mark + n);
+    p.R = (PairRec *)base;
+    p.touched = (u32 *)align256((unsigned char *)(p.R + n));
     p.K = (u32 *)align256((unsigned char *)(p.touched + n));
     p.tk = (u32 *)align256((unsigned char *)(p.K + (u64)WAVES_PER_WG * n));
     return p;
@@ -684,7 +716,8 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
                                              const u64 *tl_ptr, const uint2 *tl, u32 n,
                                              unsigned char *scratch, u64 stride, u32 *work,
                                              const u32 *order, u32 mapn, const u32 *gbase,
-                                             u32 kl, u64 *steps, u64 *Q, u64 *ni) {
+                                             u32 kl, u64 *steps, u64 *pass_cycles, u64 *Q,
+                                             u64 *ni, u64 *vacc) {
     __shared__ u32 sh_q_[GP::per_wg][3], sh_nt_[GP::per_wg], sh_next_[GP::per_wg];
     u32 *sh_q = sh_q_[GP::id()];
     if (GP::rank() == 0) { sh_q[0] = 0; sh_q[1] = 0; }
@@ -712,9 +745,11 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
         if (da < 2) continue;
         const u64 dega = da;
         u64 nsteps = 0;  // loop iterations of this thread for this source
-        for (u32 i = GP::rank(); i < da; i += GP::size) P.mark[ci[ba + i] - vb] = 1;
+        u64 t_pass = 0;  // clock at the last pass boundary (profiling)
+        for (u32 i = GP::rank(); i < da; i += GP::size) P.R[ci[ba + i] - vb].adj = 1;
         if (GP::rank() == 0) { sh_nt = 0; sh_next = 0; }
         GP::sync();
+        if (pass_cycles) pass_mark(pass_cycles, 0, t_pass);
         // wedges a - y - b, b > a
         wave_loop(&sh_next, da, [&](u32 iy) {
             const u32 say = ba + iy, y = ci[say];
@@ -724,15 +759,17 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
             for (u32 s = st0 + lane_id(); s < ey; s += WAVE) {
                 const u32 b = ci[s];
                 nsteps++;
-                u32 old = atomicAdd(&P.S[b - vb], 1u);
+                PairRec &r = P.R[b - vb];
+                u32 old = atomicAdd(&r.s, 1u);
                 if (old == 0) P.touched[atomicAdd(&sh_nt, 1u)] = b;
-                atomicAdd(&P.TA[b - vb], tay);
-                atomicAdd(&P.TB[b - vb], (u64)T[s]);
+                atomicAdd(&r.ta, tay);
+                atomicAdd(&r.tb, (u64)T[s]);
             }
         });
         GP::sync();
         if (GP::rank() == 0) sh_next = 0;
         GP::sync();
+        if (pass_cycles) pass_mark(pass_cycles, 1, t_pass);
         // wheel maps of the arcs (a, y): K(a,y,b) = |N(a) & N(y) & N(b)| for
         // b > a, from the diamonds with tip a and chord (y,z) (z in the
         // triangle list of (a,y), b in the list of (y,z), which is sorted by
@@ -803,15 +840,16 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
                 const u32 b = ci[by + pos];
                 const u64 v = c2((i64)kab);
                 q += v;
-                atomic_add_u64(&NI(b, 68), v);
-                atomicAdd(&P.E[b - vb], (u64)kab);
-                c64 += (u64)kab * ((u64)P.S[b - vb] - 2);
+                atomic_add_u64(&VACC(b, VA_68), v);
+                PairRec &r = P.R[b - vb];
+                atomicAdd(&r.e2, (u64)kab);
+                c64 += (u64)kab * ((u64)r.s - 2);
             }
             q = wave_sum_u64(q);
             c64 = wave_sum_u64(c64);
             if (lane_id() == 0) {
                 Q[say] = q;
-                atomic_add_u64(&NI(y, 64), c64);
+                atomic_add_u64(&VACC(y, VA_64), c64);
                 *ntk = 0;
             }
             l68 += q;
@@ -821,38 +859,41 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
         });
         GP::sync();
         // l68 is uniform within each wave (computed from wave sums)
-        if (lane_id() == 0) atomic_add_u64(&NI(a, 68), l68);
-        // pair terms (P.E holds 2 e)
+        if (lane_id() == 0) atomic_add_u64(&VACC(a, VA_68), l68);
+        if (pass_cycles) pass_mark(pass_cycles, 2, t_pass);
+        // pair terms (the records hold 2 e)
         const u32 nt = sh_nt;
         u64 l36 = 0, l50 = 0, l51 = 0, l63 = 0;
         for (u32 t = GP::rank(); t < nt; t += GP::size) {
             const u32 b = P.touched[t];
-            const u64 s = P.S[b - vb];
+            const PairRec &r = P.R[b - vb];
+            const u64 s = r.s;
             if (s < 2) continue;
-            const u64 adj = P.mark[b - vb];
-            const u64 e = P.E[b - vb] >> 1;
+            const u64 adj = r.adj;
+            const u64 e = r.e2 >> 1;
             const u64 cs2 = c2((i64)s), cs3 = c3((i64)s);
             l36 += cs2 * ((u64)deg[b] - 2);
             l50 += cs3;
-            l51 += (P.TB[b - vb] - adj * s) * (s - 1);
+            l51 += (r.tb - adj * s) * (s - 1);
             l63 += e * (s - 2);
-            atomic_add_u64(&NI(b, 36), cs2 * (dega - 2));
-            atomic_add_u64(&NI(b, 50), cs3);
-            atomic_add_u64(&NI(b, 51), (P.TA[b - vb] - adj * s) * (s - 1));
-            atomic_add_u64(&NI(b, 63), e * (s - 2));
+            atomic_add_u64(&VACC(b, VA_36), cs2 * (dega - 2));
+            atomic_add_u64(&VACC(b, VA_50), cs3);
+            atomic_add_u64(&VACC(b, VA_51), (r.ta - adj * s) * (s - 1));
+            atomic_add_u64(&VACC(b, VA_63), e * (s - 2));
         }
         l36 = GP::sum(l36, sh_red);
         l50 = GP::sum(l50, sh_red);
         l51 = GP::sum(l51, sh_red);
         l63 = GP::sum(l63, sh_red);
         if (GP::rank() == 0) {
-            atomic_add_u64(&NI(a, 36), l36);
-            atomic_add_u64(&NI(a, 50), l50);
-            atomic_add_u64(&NI(a, 51), l51);
-            atomic_add_u64(&NI(a, 63), l63);
+            atomic_add_u64(&VACC(a, VA_36), l36);
+            atomic_add_u64(&VACC(a, VA_50), l50);
+            atomic_add_u64(&VACC(a, VA_51), l51);
+            atomic_add_u64(&VACC(a, VA_63), l63);
             sh_next = 0;
         }
         GP::sync();
+        if (pass_cycles) pass_mark(pass_cycles, 3, t_pass);
         // centre terms
         wave_loop(&sh_next, da, [&](u32 iy) {
             const u32 say = ba + iy, y = ci[say];
@@ -861,26 +902,29 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
             u64 a49 = 0, a62 = 0;
             for (u32 s = st0 + lane_id(); s < ey; s += WAVE) {
                 const u32 b = ci[s];
-                const u32 sb = P.S[b - vb];
+                const PairRec &r = P.R[b - vb];
+                const u32 sb = r.s;
                 nsteps++;
                 if (sb >= 2) {
                     a49 += c2((i64)sb - 1);
-                    a62 += P.E[b - vb] >> 1;
+                    a62 += r.e2 >> 1;
                 }
             }
             a49 = wave_sum_u64(a49);
             a62 = wave_sum_u64(a62);
             if (lane_id() == 0) {
-                atomic_add_u64(&NI(y, 49), a49);
-                atomic_add_u64(&NI(y, 62), a62);
+                atomic_add_u64(&VACC(y, VA_49), a49);
+                atomic_add_u64(&VACC(y, VA_62), a62);
             }
         });
         GP::sync();
         for (u32 t = GP::rank(); t < nt; t += GP::size) {
             const u32 b = P.touched[t];
-            P.S[b - vb] = 0; P.E[b - vb] = 0; P.TA[b - vb] = 0; P.TB[b - vb] = 0;
+            PairRec &r = P.R[b - vb];
+            r.s = 0; r.ta = 0; r.tb = 0; r.e2 = 0;
         }
-        for (u32 i = GP::rank(); i < da; i += GP::size) P.mark[ci[ba + i] - vb] = 0;
+        for (u32 i = GP::rank(); i < da; i += GP::size) P.R[ci[ba + i] - vb].adj = 0;
+        if (pass_cycles) pass_mark(pass_cycles, 4, t_pass);
         if (steps) {  // per-source work, the training target of the scheduler
             u64 tot = GP::sum(nsteps, sh_red);
             if (GP::rank() == 0) steps[a] += tot;
@@ -953,9 +997,16 @@ __device__ inline bool hset_has(const u32 *hs, u32 x) {
         h = (h + 1) & (C5_HSET - 1);
     }
 }
-__device__ inline void hset_clear(u32 *hs) {
+// Empties the set by clearing exactly the slots of N+(k): each lane finds its
+// own keys (still present, since only it removes them) and zeroes them.
+__device__ inline void hset_clear(u32 *hs, u32 k, const u64 *out_ptr, const u32 *out_nbr) {
     wave_sync();
-    for (u32 i = lane_id(); i < C5_HSET; i += WAVE) hs[i] = 0;
+    for (u64 q = out_ptr[k] + lane_id(); q < out_ptr[k + 1]; q += WAVE) {
+        const u32 key = out_nbr[q] + 1;
+        u32 h = hset_slot(key);
+        while (hs[h] != key) h = (h + 1) & (C5_HSET - 1);
+        hs[h] = 0;
+    }
     wave_sync();
 }
 
@@ -965,7 +1016,7 @@ __global__ void __launch_bounds__(WG) k_c5(const u32 *rp, const u32 *ci, const u
                                           const u32 *out_slot, const u32 *Tin, const u32 *Tmid,
                                           u32 n, unsigned char *scratch, u64 stride, u32 *work,
                                           const u32 *order, u32 mapn, const u32 *gbase,
-                                          u64 *steps, u64 *ni) {
+                                          u64 *steps, u64 *cacc) {
     __shared__ u32 sh_q_[GP::per_wg][3], sh_nt_[GP::per_wg], sh_next_[GP::per_wg];
     u32 *sh_q = sh_q_[GP::id()];
     if (GP::rank() == 0) { sh_q[0] = 0; sh_q[1] = 0; }
@@ -1019,7 +1070,7 @@ __global__ void __launch_bounds__(WG) k_c5(const u32 *rp, const u32 *ci, const u
                         atomic_add_u64(&C.CI[i - vb], (kin ? 1 : 0) + jl);
                     }
                 }
-                if (use_hs) hset_clear(hs);
+                if (use_hs) hset_clear(hs, k, out_ptr, out_nbr);
             }
         });
         GP::sync();
@@ -1068,14 +1119,14 @@ __global__ void __launch_bounds__(WG) k_c5(const u32 *rp, const u32 *ci, const u
                         accj += (u64)C.Wm[i - vb] - (kin ? 1 : 0) - jl;
                     }
                     accj = wave_sum_u64(accj);
-                    if (lane_id() == 0) atomic_add_u64(&NI(j, 34), accj);
+                    if (lane_id() == 0) atomic_add_u64(&cacc[j], accj);
                     acck += accj;
                 }
-                if (lane_id() == 0) atomic_add_u64(&NI(k, 34), acck);
-                if (use_hs) hset_clear(hs);
+                if (lane_id() == 0) atomic_add_u64(&cacc[k], acck);
+                if (use_hs) hset_clear(hs, k, out_ptr, out_nbr);
             }
             accw = wave_sum_u64(accw);
-            if (lane_id() == 0) atomic_add_u64(&NI(w, 34), accw);
+            if (lane_id() == 0) atomic_add_u64(&cacc[w], accw);
         });
         GP::sync();
         // credits of i (summed over its 3-paths) and of l
@@ -1085,10 +1136,10 @@ __global__ void __launch_bounds__(WG) k_c5(const u32 *rp, const u32 *ci, const u
             const u32 i = C.touched[t];
             const u64 v = C.P[i - vb] * (u64)C.Wm[i - vb] - C.CI[i - vb];
             accl += v;
-            atomic_add_u64(&NI(i, 34), v);
+            atomic_add_u64(&cacc[i], v);
         }
         accl = GP::sum(accl, sh_red);
-        if (GP::rank() == 0) atomic_add_u64(&NI(l, 34), accl);
+        if (GP::rank() == 0) atomic_add_u64(&cacc[l], accl);
         if (steps) {
             const u64 tot = GP::sum(nsteps, sh_red);
             if (GP::rank() == 0) steps[l] += tot;

@@ -42,7 +42,7 @@ struct Layout {
     u64 p1_end = 0;
     // phase 2
     Buf tri_c, tri_sab, tri_sac, tri_sbc, T, Tin, Tmid, tllen, tlptr, tlcur, tl, E7, E9, C4e,
-        K4e, Q, K4t, Tv, N1, C4v, K4v, ni, feat, pred, sbin, shist, order, scratch;
+        K4e, Q, K4t, Tv, N1, C4v, K4v, ni, vacc, cacc, feat, pred, sbin, shist, order, scratch;
     u64 total = 0;
     u64 stride = 0;
     u32 nwg = 0;
@@ -84,9 +84,9 @@ void layout_phase1(Layout &L, u32 n, u64 m) {
 }
 
 u64 pair_stride(u32 n) {
-    // S u32, E/TA/TB u64, mark u8, touched u32, 4 wave maps + lists u32
-    return align_up(4ull * n, 256) + 3 * align_up(8ull * n, 256) + align_up(n, 256) +
-           align_up(4ull * n, 256) + 2 * align_up(4ull * WAVES_PER_WG * n, 256) + 256;
+    // 32-byte records, touched u32, 4 wave maps + lists u32
+    return align_up(32ull * n, 256) + align_up(4ull * n, 256) +
+           2 * align_up(4ull * WAVES_PER_WG * n, 256) + 256;
 }
 u64 clique_stride(u32 dmax) {
     u64 W = (dmax + 63) / 64;
@@ -121,6 +121,8 @@ void layout_phase2(Layout &L, u32 n, u32 mapn, u64 m, u64 ntri, u32 dmax, int k_
     place(c, L.C4v, 8ull * n + 8);
     place(c, L.K4v, 8ull * n + 8);
     place(c, L.ni, ni_in_out ? 0 : 8ull * ORB_NORB * n + 8);
+    place(c, L.vacc, 64ull * n + 64);
+    place(c, L.cacc, 8ull * n + 8);
     place(c, L.feat, 12ull * n + 12);
     place(c, L.pred, 4ull * n + 4);
     place(c, L.sbin, 4ull * n + 4);
@@ -189,10 +191,10 @@ int zero_ranges(int which, u32 n, ZeroRange *r) {
         r[0] = {0, a4};
         return 1;
     }
-    if (which == 1) {  // pair sweep: S, E, TA, TB, mark ... then the wave maps K
-        u64 kof = a4 + 3 * a8 + a1 + a4;
-        r[0] = {0, a4 + 3 * a8 + a1};
-        r[1] = {kof, align_up(4ull * WAVES_PER_WG * n, 256)};
+    if (which == 1) {  // pair sweep: records ... then the wave maps K
+        const u64 a32 = align_up(32ull * n, 256);
+        r[0] = {0, a32};
+        r[1] = {a32 + a4, align_up(4ull * WAVES_PER_WG * n, 256)};
         return 2;
     }
     // 5-cycles: Wm, P, CI, (touched), mark
@@ -479,6 +481,7 @@ int count_impl(const u32 *rp, const u32 *ci, u32 n, u64 m, const u64 *vptr, u32 
     u64 *Tv = at<u64>(ws, L.Tv), *N1 = at<u64>(ws, L.N1), *C4v = at<u64>(ws, L.C4v),
         *K4v = at<u64>(ws, L.K4v);
     u64 *ni = ni_in_out ? counts : at<u64>(ws, L.ni);
+    u64 *vacc = at<u64>(ws, L.vacc), *cacc = at<u64>(ws, L.cacc);
     unsigned char *scratch = at<unsigned char>(ws, L.scratch);
     const u32 *gbase = vptr ? at<u32>(ws, L.gbase) : nullptr;
     // LDS capacities: clique bit rows up to the largest out-degree, wheel
@@ -603,19 +606,21 @@ int count_impl(const u32 *rp, const u32 *ci, u32 n, u64 m, const u64 *vptr, u32 
         if (rc) return rc;
         tm.mark("zero_pairs");
         WITH_GP(wave_groups, k_pairs<GPT><<<L.nwg, WG, pair_lds, s>>>(rp, ci, src, rev, deg, T, tlptr, tl, n, scratch, L.stride,
-                                     work + wi++, order, mapn, gbase, pair_kl, steps_out, Q, ni));
+                                     work + wi++, order, mapn, gbase, pair_kl, steps_out,
+                                     opts ? (u64 *)opts->pass_cycles_out : nullptr, Q, ni,
+                                     vacc));
         HCHK(hipGetLastError());
         tm.mark("pairs");
         rc = zero_scratch(2, mapn, scratch, L, grp5, s);
         if (rc) return rc;
         tm.mark("zero_c5");
         WITH_GP(wave_groups, k_c5<GPT><<<c5_wg, WG, 0, s>>>(rp, ci, key, outptr, outnbr, outslot, Tin, Tmid, n, scratch,
-                                  L.stride, work + wi++, order, mapn, gbase, steps_out, ni));
+                                  L.stride, work + wi++, order, mapn, gbase, steps_out, cacc));
         HCHK(hipGetLastError());
         tm.mark("c5");
     }
     WITH_GROUP(gsz, k_vert1<GG><<<grid_for((u64)n * GG, WG), WG, 0, s>>>(
-                        rp, ci, rev, deg, T, Tv, N1, C4v, K4v, C4e, K4e, E9, Q, n, ni));
+                        rp, ci, rev, deg, T, Tv, N1, C4v, K4v, C4e, K4e, E9, Q, vacc, cacc, n, ni));
     if (k_max >= 5)
         WITH_GROUP(gsz, k_vert2<GG><<<grid_for((u64)n * GG, WG), WG, 0, s>>>(rp, ci, deg, Tv, N1,
                                                                             n, ni));

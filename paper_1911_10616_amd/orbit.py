@@ -38,7 +38,7 @@ class _Opts(ctypes.Structure):
     _fields_ = [("flags", ctypes.c_uint32), ("num_wg", ctypes.c_uint32),
                 ("schedule", ctypes.c_uint32), ("groups", ctypes.c_uint32),
                 ("mlp_weights", ctypes.c_void_p), ("features_out", ctypes.c_void_p),
-                ("steps_out", ctypes.c_void_p)]
+                ("steps_out", ctypes.c_void_p), ("pass_cycles_out", ctypes.c_void_p)]
 
 
 def _load():
@@ -126,10 +126,11 @@ def _ptr(t):
 
 
 def _opts(noninduced=False, timing=False, num_wg=0, schedule=SCHED_ID, mlp_weights=None,
-          features_out=None, steps_out=None, groups=0):
+          features_out=None, steps_out=None, groups=0, pass_cycles_out=None):
     f = (ORB_NONINDUCED if noninduced else 0) | (ORB_TIMING if timing else 0)
     g = GROUPS[groups] if isinstance(groups, str) else int(groups)
-    return _Opts(f, num_wg, schedule, g, _ptr(mlp_weights), _ptr(features_out), _ptr(steps_out))
+    return _Opts(f, num_wg, schedule, g, _ptr(mlp_weights), _ptr(features_out), _ptr(steps_out),
+                 _ptr(pass_cycles_out))
 
 
 def workspace_bytes(row_ptr, col_idx, k_max=5, noninduced=False, num_wg=0, stream=None,
@@ -157,12 +158,13 @@ class Counter:
 
     def __init__(self, row_ptr, col_idx, k_max=5, noninduced=False, num_wg=0, stream=None,
                  schedule="id", mlp_weights=None, features_out=None, steps_out=None,
-                 groups="auto"):
+                 groups="auto", pass_cycles_out=None):
         """schedule: "id", "static" or "mlp" (source order of the per-source
         kernels; needs mlp_weights, a float32 device tensor of MLP_PARAMS
         values, for "mlp").  features_out (float32 [n, 3]) and steps_out
         (int64 [n], uint64 bits) receive the cost features and per-source
-        pair-sweep step counts on every run when given."""
+        pair-sweep step counts on every run when given; pass_cycles_out (int64
+        [4]) accumulates the pair sweep's per-pass clock cycles."""
         import torch
         self.rp, self.ci = _dev_csr(row_ptr, col_idx)
         self.n = self.rp.numel() - 1
@@ -173,8 +175,8 @@ class Counter:
             raise OrbError(-1, "k_max")
         sched = SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule)
         extra = dict(schedule=sched, mlp_weights=mlp_weights, features_out=features_out,
-                     steps_out=steps_out, groups=groups)
-        self._keep = (mlp_weights, features_out, steps_out)
+                     steps_out=steps_out, groups=groups, pass_cycles_out=pass_cycles_out)
+        self._keep = (mlp_weights, features_out, steps_out, pass_cycles_out)
         self.opts = _opts(noninduced, False, num_wg, **extra)
         self.topts = _opts(noninduced, True, num_wg, **extra)
         self.stream = stream
