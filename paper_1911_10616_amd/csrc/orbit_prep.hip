@@ -88,16 +88,34 @@ __global__ void k_peel_step(const u32 *rp, const u32 *ci, u32 n, int *pdeg, u32 
     const u32 round = st->round;
     if (st->alive == 0) return;
     if (fs == 0) {
-        for (u64 u = GTID; u < n; u += GSTRIDE) {
-            if (rnd[u] != UNSET) continue;
-            int d = pdeg[u];
-            if (d <= level) {
-                rnd[u] = round;
-                u32 pos = atomicAdd(&st->fsize[nxt], 1u);
-                front[(u64)nxt * n + pos] = (u32)u;
-            } else {
-                atomicMin(&st->minalive, (u32)d);
+        // every lane of a wave runs the same iterations, so the frontier
+        // appends and the minimum are combined per wave (one atomic each)
+        for (u64 base = GTID - lane_id(); base < n; base += GSTRIDE) {
+            const u64 u = base + lane_id();
+            bool take = false;
+            u32 dmin = 0xffffffffu;
+            if (u < n && rnd[u] == UNSET) {
+                const int d = pdeg[u];
+                if (d <= level) take = true;
+                else dmin = (u32)d;
             }
+            const u64 mask = __ballot(take);
+            if (mask) {
+                u32 basepos = 0;
+                const u32 leader = (u32)__ffsll((long long)mask) - 1;
+                if (lane_id() == leader) basepos = atomicAdd(&st->fsize[nxt], (u32)__popcll(mask));
+                basepos = __shfl(basepos, (int)leader, WAVE);
+                if (take) {
+                    rnd[u] = round;
+                    front[(u64)nxt * n + basepos + __popcll(mask & ((1ull << lane_id()) - 1ull))] =
+                        (u32)u;
+                }
+            }
+            for (int off = WAVE / 2; off > 0; off >>= 1) {
+                const u32 o = __shfl_xor(dmin, off, WAVE);
+                dmin = o < dmin ? o : dmin;
+            }
+            if (lane_id() == 0 && dmin != 0xffffffffu) atomicMin(&st->minalive, dmin);
         }
     } else {
         for (u64 i = GTID / G; i < fs; i += GSTRIDE / G) {
