@@ -223,7 +223,8 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(this build has no multi-GPU path)", file=sys.stderr)
+              "(the library counts on one GPU; sharding over several is not implemented)",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
