@@ -161,3 +161,25 @@ def test_plan_replays_match_eager(orbit, batched):
         assert int(x) == (1 << 20) * ((1 << 20) - 1) // 2
     plan.close()
     np.testing.assert_array_equal(c.run().cpu().numpy(), ref)
+
+
+@pytest.mark.slow
+def test_full_batch_sampled_graphs_against_oracle(orbit):
+    """The 100,000-graph batch at full size, in the configuration bench.py
+    times (autotuned), with 20 sampled graphs checked one by one against the
+    oracle and the degree identities checked on every vertex."""
+    vptr, rp, ci = gg.workload("batch100k")
+    _say("batch100k generated", len(rp) - 1, ci.size // 2)
+    bc = orbit.BatchCounter(vptr, rp, ci, 5)
+    cfg = bc.autotune((512, 1024, 2048, 4096))
+    _say("autotuned", cfg)
+    got = bc.run().cpu().numpy().view(np.uint64)
+    d = np.diff(rp).astype(np.uint64)
+    np.testing.assert_array_equal(got[:, 0], d)
+    assert np.array_equal(got[:, 2] + got[:, 3], d * (d - np.uint64(1)) // np.uint64(2))
+    rng = np.random.default_rng(2024)
+    for g in rng.choice(len(vptr) - 1, size=20, replace=False):
+        a, b = int(vptr[g]), int(vptr[g + 1])
+        np.testing.assert_array_equal(got[a:b], oracle.induced_counts(*_graph(vptr, rp, ci, g),
+                                                                     threads=8),
+                                      err_msg=f"graph {g}")
