@@ -70,6 +70,12 @@ extern "C" {
 /* option flags */
 #define ORB_NONINDUCED 0x1u /* return non-induced counts DM(u, theta) */
 #define ORB_TIMING 0x2u     /* record per-phase times (orbit_last_phase_times) */
+#define ORB_RELABEL 0x4u    /* count on a copy of the graph renumbered heaviest degree
+                               class first (rows, maps and per-vertex data of the hubs
+                               together: faster on graphs whose ids are unrelated to
+                               degree); the counts come back under the caller's ids.  One
+                               graph only (not batched), not with features_out/steps_out;
+                               the workspace grows by about 8m + 40n bytes. */
 
 /* order in which the per-source kernels take their sources (the counts
  * are the same under every schedule; only the work balance changes) */

@@ -286,8 +286,10 @@ __global__ void k_vert2(const u32 *rp, const u32 *ci, const u32 *deg, const u64 
 // spread over all banks), and the first K columns go out with coalesced
 // stores (out may alias ni when K == 73).
 #define XF_ROWS 64
+// With a relabelling, row r of ni belongs to vertex orig[r] of the caller's
+// graph and is written there (orig == NULL: the identity).
 __global__ void __launch_bounds__(WAVE) k_transform(u64 *ni, u32 n, int K, int induced,
-                                                    u64 *out) {
+                                                    const u32 *orig, u64 *out) {
     __shared__ u64 tile[XF_ROWS * ORB_NORB];
     const u32 lane = threadIdx.x;
     for (u64 base = (u64)blockIdx.x * XF_ROWS; base < n; base += (u64)gridDim.x * XF_ROWS) {
@@ -306,7 +308,12 @@ __global__ void __launch_bounds__(WAVE) k_transform(u64 *ni, u32 n, int K, int i
         }
         __syncthreads();
         u64 *dst = out + base * K;
-        if (K == ORB_NORB) {
+        if (orig) {
+            for (u32 i = lane; i < rows * (u32)K; i += WAVE) {
+                const u32 r = i / K, c = i % K;
+                out[(u64)orig[base + r] * K + c] = tile[r * ORB_NORB + c];
+            }
+        } else if (K == ORB_NORB) {
             for (u32 i = lane; i < rows * ORB_NORB; i += WAVE) dst[i] = tile[i];
         } else {
             for (u32 i = lane; i < rows * (u32)K; i += WAVE)

@@ -23,6 +23,7 @@ const int kMaxPhases = 24;
 const u32 kWaveGroupMaxMap = 4096;
 const u32 kWaveGroupMaxOut = 64;
 const u64 kMaxDynLds = 64 << 10;  // dynamic LDS per workgroup
+const u32 kRelabelSortWg = 64;     // workgroups sorting the long rows of a relabelled CSR
 thread_local float g_phase_ms[kMaxPhases];
 thread_local const char *g_phase_name[kMaxPhases];
 thread_local int g_nphase = 0;
@@ -39,6 +40,8 @@ struct Layout {
     // phase 1
     Buf state, deg, src, rev, rnd, pdeg, front, key, outdeg, outptr, outnbr, outslot, tcnt,
         triptr, bsum, gbase;
+    // relabelling (ORB_RELABEL)
+    Buf rl_rp, rl_ci, rl_order, rl_newid, rl_bin, rl_ndeg, rl_hist, rl_rp64, rl_queue, rl_bitmaps;
     u64 p1_end = 0;
     // phase 2
     Buf tri_c, tri_sab, tri_sac, tri_sbc, T, Tin, Tmid, tllen, tlptr, tlcur, tl, E7, E9, C4e,
@@ -60,7 +63,9 @@ void place(u64 &cur, Buf &b, u64 bytes) {
 
 u64 nblocks_scan(u64 len) { return (len + SCAN_TILE - 1) / SCAN_TILE; }
 
-void layout_phase1(Layout &L, u32 n, u64 m) {
+bool wants_relabel(const orb_opts *opts) { return opts && (opts->flags & ORB_RELABEL); }
+
+void layout_phase1(Layout &L, u32 n, u64 m, bool relabel = false) {
     const u64 M2 = 2 * m;
     u64 c = 0;
     place(c, L.state, sizeof(DevState));
@@ -80,6 +85,18 @@ void layout_phase1(Layout &L, u32 n, u64 m) {
     u64 maxlen = M2 + 1 > (u64)n + 1 ? M2 + 1 : (u64)n + 1;
     place(c, L.bsum, 8ull * (nblocks_scan(maxlen) + 1));
     place(c, L.gbase, 4ull * n + 4);
+    if (relabel) {
+        place(c, L.rl_rp, 4ull * (n + 1));
+        place(c, L.rl_ci, 4ull * M2 + 4);
+        place(c, L.rl_order, 4ull * n + 4);
+        place(c, L.rl_newid, 4ull * n + 4);
+        place(c, L.rl_bin, 4ull * n + 4);
+        place(c, L.rl_ndeg, 4ull * n + 4);
+        place(c, L.rl_hist, 4ull * SCHED_BINS);
+        place(c, L.rl_rp64, 8ull * (n + 1));
+        place(c, L.rl_queue, 4ull * n + 4);
+        place(c, L.rl_bitmaps, 4ull * kRelabelSortWg * ((n + 31) / 32 + 1));
+    }
     L.p1_end = c;
 }
 
@@ -419,6 +436,57 @@ int run_phase1(const u32 *rp, const u32 *ci, u32 n, u64 m, const u64 *vptr, u32 
     return ORB_OK;
 }
 
+// ORB_RELABEL: validate the caller's CSR (the checks of phase 1), then build
+// the relabelled CSR (heaviest degree class first, rows sorted) in the
+// workspace; phase 1 validates that one again.
+int relabel_input(const u32 *rp, const u32 *ci, u32 n, u64 m, void *ws, const Layout &L,
+                  hipStream_t s, DevState *hs, bool cap, const u32 **nrp_out,
+                  const u32 **nci_out) {
+    const u64 M2 = 2 * m;
+    DevState *st = at<DevState>(ws, L.state);
+    u32 *deg = at<u32>(ws, L.deg), *src = at<u32>(ws, L.src), *rev = at<u32>(ws, L.rev);
+    u64 *bsum = at<u64>(ws, L.bsum);
+    int rc = zero_u64(st, sizeof(DevState) / 8, s);
+    if (rc) return rc;
+    k_check_rowptr<<<grid_for(n, WG), WG, 0, s>>>(rp, n, M2, st);
+    HCHK(hipGetLastError());
+    if (!cap) {
+        rc = read_state(st, hs, s);
+        if (rc) return rc;
+        if (hs->err) return err_to_status(hs->err);
+    }
+    k_src_deg<<<grid_waves(n), WG, 0, s>>>(rp, n, src, deg);
+    k_rev<<<grid_for(M2, WG), WG, 0, s>>>(rp, ci, src, nullptr, n, M2, rev, st);
+    HCHK(hipGetLastError());
+    if (!cap) {
+        rc = read_state(st, hs, s);
+        if (rc) return rc;
+        if (hs->err) return err_to_status(hs->err);
+    }
+    u32 *nrp = at<u32>(ws, L.rl_rp), *nci = at<u32>(ws, L.rl_ci);
+    u32 *order = at<u32>(ws, L.rl_order), *newid = at<u32>(ws, L.rl_newid);
+    u32 *bin = at<u32>(ws, L.rl_bin), *ndeg = at<u32>(ws, L.rl_ndeg);
+    u32 *hist = at<u32>(ws, L.rl_hist), *queue = at<u32>(ws, L.rl_queue);
+    u64 *nrp64 = at<u64>(ws, L.rl_rp64);
+    rc = zero_u64(hist, SCHED_BINS / 2, s);
+    if (rc) return rc;
+    k_deg_bins<<<grid_for(n, WG), WG, 0, s>>>(deg, n, bin, hist);
+    k_sched_offsets<<<1, 64, 0, s>>>(hist);
+    k_sched_scatter<<<grid_for(n, WG), WG, 0, s>>>(bin, n, hist, order);
+    k_relabel_index<<<grid_for(n, WG), WG, 0, s>>>(order, deg, n, newid, ndeg);
+    HCHK(hipGetLastError());
+    rc = scan<u32>(ndeg, n, nrp64, bsum, st, s);
+    if (rc) return rc;
+    k_relabel_fill<<<grid_waves(n), WG, 0, s>>>(rp, ci, order, newid, nrp64, n, nrp, nci);
+    u32 *qlen = st->work + 14;
+    k_row_sort_small<<<grid_waves(n), WG, 0, s>>>(nrp, n, nci, queue, qlen);
+    k_row_sort_wg<<<kRelabelSortWg, WG, 0, s>>>(nrp, nci, queue, qlen, at<u32>(ws, L.rl_bitmaps), n);
+    HCHK(hipGetLastError());
+    *nrp_out = nrp;
+    *nci_out = nci;
+    return ORB_OK;
+}
+
 int count_impl(const u32 *rp, const u32 *ci, u32 n, u64 m, const u64 *vptr, u32 B, int k_max,
                u64 *counts, void *ws,
                u64 ws_bytes, u64 *ws_required, hipStream_t s, const orb_opts *opts,
@@ -427,7 +495,9 @@ int count_impl(const u32 *rp, const u32 *ci, u32 n, u64 m, const u64 *vptr, u32 
     const u32 flags = opts ? opts->flags : 0u;
     const int K = orbit_num_orbits(k_max);
     if (!K) return ORB_E_INVALID_ARG;
-    if (flags & ~(ORB_NONINDUCED | ORB_TIMING)) return ORB_E_INVALID_ARG;
+    if (flags & ~(ORB_NONINDUCED | ORB_TIMING | ORB_RELABEL)) return ORB_E_INVALID_ARG;
+    const bool relabel = (flags & ORB_RELABEL) != 0;
+    if (relabel && (vptr || opts->features_out || opts->steps_out)) return ORB_E_INVALID_ARG;
     const u32 sched = opts ? opts->schedule : ORB_SCHED_ID;
     if (sched > ORB_SCHED_MLP || (opts && opts->groups > ORB_GROUPS_WAVE))
         return ORB_E_INVALID_ARG;
@@ -435,7 +505,7 @@ int count_impl(const u32 *rp, const u32 *ci, u32 n, u64 m, const u64 *vptr, u32 
     if (2 * m >= (1ull << 32)) return ORB_E_INVALID_ARG;
     if (!rp || (m && !ci) || (!counts && !query_only && n)) return ORB_E_INVALID_ARG;
     Layout L;
-    layout_phase1(L, n, m);
+    layout_phase1(L, n, m, relabel);
     if (ws_bytes < L.p1_end || !ws) {
         if (ws_required) *ws_required = L.p1_end;
         return ORB_E_WORKSPACE;
@@ -443,11 +513,21 @@ int count_impl(const u32 *rp, const u32 *ci, u32 n, u64 m, const u64 *vptr, u32 
     Timer tm((flags & ORB_TIMING) && !query_only && !cap, s);
     DevState hs;
     memset(&hs, 0, sizeof hs);
+    const u32 *orig = nullptr;  // relabelled vertex -> caller's vertex
+    if (relabel && n) {
+        const u32 *nrp = nullptr, *nci = nullptr;
+        int rc0 = relabel_input(rp, ci, n, m, ws, L, s, &hs, cap, &nrp, &nci);
+        if (rc0) return rc0;
+        rp = nrp;
+        ci = nci;
+        orig = at<u32>(ws, L.rl_order);
+        tm.mark("relabel");
+    }
     int rc = run_phase1(rp, ci, n, m, vptr, B, ws, L, s, &hs, tm, pl);
     if (rc) return rc;
     const u64 ntri = hs.ntri;
     const u32 dmax = hs.maxlevel + 1;
-    const bool ni_in_out = (K == ORB_NORB);
+    const bool ni_in_out = (K == ORB_NORB) && !relabel;
     const u32 mapn = vptr ? (hs.gmax ? hs.gmax : 1) : n;
     // per-source execution groups: a wave per source for small maps (many
     // light sources), the whole workgroup per source otherwise
@@ -625,7 +705,7 @@ int count_impl(const u32 *rp, const u32 *ci, u32 n, u64 m, const u64 *vptr, u32 
         WITH_GROUP(gsz, k_vert2<GG><<<grid_for((u64)n * GG, WG), WG, 0, s>>>(rp, ci, deg, Tv, N1,
                                                                             n, ni));
     k_transform<<<grid_for(n, XF_ROWS), WAVE, 0, s>>>(ni, n, K, (flags & ORB_NONINDUCED) ? 0 : 1,
-                                                     counts);
+                                                     orig, counts);
     HCHK(hipGetLastError());
     tm.mark("combine");
     if (flags & ORB_TIMING) {
@@ -674,7 +754,7 @@ int orbit_workspace_query(const uint32_t *row_ptr, const uint32_t *col_idx, uint
     if (!bytes || !orbit_num_orbits(k_max)) return ORB_E_INVALID_ARG;
     if (2 * m >= (1ull << 32)) return ORB_E_INVALID_ARG;
     Layout L;
-    layout_phase1(L, n, m);
+    layout_phase1(L, n, m, wants_relabel(opts));
     void *tmp = nullptr;
     if (hipMalloc(&tmp, L.p1_end) != hipSuccess) return ORB_E_DEVICE;
     u64 req = 0;

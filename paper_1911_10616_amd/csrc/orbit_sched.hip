@@ -226,3 +226,144 @@ __global__ void k_sched_offsets(u32 *hist) {
 __global__ void k_sched_scatter(const u32 *bin, u32 n, u32 *cursor, u32 *order) {
     for (u64 u = GTID; u < n; u += GSTRIDE) order[atomicAdd(&cursor[bin[u]], 1u)] = (u32)u;
 }
+
+// ---- relabelling (ORB_RELABEL): vertices renumbered heaviest first, by the
+// same degree classes as the static schedule (bins of 4 log2(1+d)), so that
+// the hubs' rows, maps and per-vertex data sit together.  The counts are
+// computed on the relabelled graph and written back to the original ids.
+__global__ void k_deg_bins(const u32 *deg, u32 n, u32 *bin, u32 *hist) {
+    __shared__ u32 h[SCHED_BINS];
+    for (u32 i = threadIdx.x; i < SCHED_BINS; i += WG) h[i] = 0;
+    __syncthreads();
+    for (u64 u = GTID; u < n; u += GSTRIDE) {
+        const u32 b = cost_bin(log2f(1.0f + (float)deg[u]));
+        bin[u] = b;
+        atomicAdd(&h[b], 1u);
+    }
+    __syncthreads();
+    for (u32 i = threadIdx.x; i < SCHED_BINS; i += WG)
+        if (h[i]) atomicAdd(&hist[i], h[i]);
+}
+
+// newid[order[i]] = i; ndeg[i] = d(order[i])
+__global__ void k_relabel_index(const u32 *order, const u32 *deg, u32 n, u32 *newid,
+                                u32 *ndeg) {
+    for (u64 i = GTID; i < n; i += GSTRIDE) {
+        const u32 u = order[i];
+        newid[u] = (u32)i;
+        ndeg[i] = deg[u];
+    }
+}
+
+// row i of the relabelled CSR: the new ids of the neighbours of order[i]
+// (unsorted; k_row_sort_* sort every row), one wave per row
+__global__ void k_relabel_fill(const u32 *rp, const u32 *ci, const u32 *order,
+                               const u32 *newid, const u64 *nrp64, u32 n, u32 *nrp,
+                               u32 *nci) {
+    for (u64 i = GWAVE; i < n; i += NWAVES) {
+        const u32 u = order[i];
+        const u32 b = rp[u], e = rp[u + 1];
+        const u64 o = nrp64[i];
+        if (lane_id() == 0) {
+            nrp[i] = (u32)o;
+            if (i + 1 == n) nrp[n] = (u32)nrp64[n];
+        }
+        for (u32 s = b + lane_id(); s < e; s += WAVE) nci[o + (s - b)] = newid[ci[s]];
+    }
+}
+
+// Sorting the rows of the relabelled CSR: rows of up to 64 entries by one
+// wave in registers (bitonic over lanes); longer rows are queued for
+// k_row_sort_wg.
+__global__ void k_row_sort_small(const u32 *nrp, u32 n, u32 *nci, u32 *queue, u32 *qlen) {
+    const u32 lane = lane_id();
+    for (u64 i = GWAVE; i < n; i += NWAVES) {
+        const u32 b = nrp[i], L = nrp[i + 1] - b;
+        if (L < 2) continue;
+        if (L > WAVE) {
+            if (lane == 0) queue[atomicAdd(qlen, 1u)] = (u32)i;
+            continue;
+        }
+        u32 key = 0xffffffffu;
+        if (lane < L) key = nci[b + lane];
+        for (u32 k = 2; k <= WAVE; k <<= 1) {
+            for (u32 j = k >> 1; j > 0; j >>= 1) {
+                const u32 other = __shfl_xor(key, (int)j, WAVE);
+                const bool keep_min = ((lane & j) == 0) == ((lane & k) == 0);
+                key = keep_min ? (key < other ? key : other) : (key > other ? key : other);
+            }
+        }
+        if (lane < L) nci[b + lane] = key;
+    }
+}
+
+// One workgroup per queued row: up to 4096 entries by bitonic sort in LDS;
+// longer rows (ids distinct, below n) by marking a bitmap of n bits in the
+// workgroup's scratch and reading the marked ids back in order.
+#ifndef ROW_SORT_LDS
+#define ROW_SORT_LDS 4096
+#endif
+__global__ void __launch_bounds__(WG) k_row_sort_wg(const u32 *nrp, u32 *nci, const u32 *queue,
+                                                   const u32 *qlen, u32 *bitmaps, u32 n) {
+    __shared__ u32 sk[ROW_SORT_LDS];
+    __shared__ u32 part[WG];
+    const u32 nw = (n + 31) / 32;
+    u32 *bm = bitmaps + (u64)blockIdx.x * nw;
+    const u32 cnt = *qlen;
+    for (u32 qi = blockIdx.x; qi < cnt; qi += gridDim.x) {
+        const u32 row = queue[qi];
+        const u32 b = nrp[row], L = nrp[row + 1] - b;
+        u32 *p = nci + b;
+        if (L <= ROW_SORT_LDS) {
+            u32 P = 128;
+            while (P < L) P <<= 1;
+            for (u32 i = threadIdx.x; i < P; i += WG) sk[i] = i < L ? p[i] : 0xffffffffu;
+            __syncthreads();
+            for (u32 k = 2; k <= P; k <<= 1) {
+                for (u32 j = k >> 1; j > 0; j >>= 1) {
+                    for (u32 i = threadIdx.x; i < P; i += WG) {
+                        const u32 ij = i ^ j;
+                        if (ij > i) {
+                            const u32 x = sk[i], y = sk[ij];
+                            const bool asc = (i & k) == 0;
+                            if ((x > y) == asc) { sk[i] = y; sk[ij] = x; }
+                        }
+                    }
+                    __syncthreads();
+                }
+            }
+            for (u32 i = threadIdx.x; i < L; i += WG) p[i] = sk[i];
+            __syncthreads();
+            continue;
+        }
+        for (u32 w = threadIdx.x; w < nw; w += WG) bm[w] = 0;
+        __syncthreads();
+        for (u32 i = threadIdx.x; i < L; i += WG) {
+            const u32 v = p[i];
+            atomicOr(&bm[v >> 5], 1u << (v & 31));
+        }
+        __syncthreads();
+        const u32 per = (nw + WG - 1) / WG;
+        const u32 w0 = threadIdx.x * per, w1 = w0 + per < nw ? w0 + per : nw;
+        u32 c = 0;
+        for (u32 w = w0; w < w1; w++) c += __popc(bm[w]);
+        part[threadIdx.x] = c;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            u32 run = 0;
+            for (u32 t = 0; t < WG; t++) { const u32 v = part[t]; part[t] = run; run += v; }
+        }
+        __syncthreads();
+        u32 r = part[threadIdx.x];
+        for (u32 w = w0; w < w1; w++) {
+            u32 bits = bm[w];
+            while (bits) {
+                const u32 bb = __ffs(bits) - 1;
+                bits &= bits - 1;
+                p[r++] = w * 32 + bb;
+            }
+        }
+        __syncthreads();
+    }
+}
+

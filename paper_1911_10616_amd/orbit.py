@@ -16,6 +16,7 @@ from .build import LIB
 NORB = 73
 ORB_NONINDUCED = 0x1
 ORB_TIMING = 0x2
+ORB_RELABEL = 0x4
 SCHED_ID, SCHED_STATIC, SCHED_MLP = 0, 1, 2
 SCHEDULES = {"id": SCHED_ID, "static": SCHED_STATIC, "mlp": SCHED_MLP}
 GROUPS = {"auto": 0, "wg": 1, "wave": 2}
@@ -126,20 +127,21 @@ def _ptr(t):
 
 
 def _opts(noninduced=False, timing=False, num_wg=0, schedule=SCHED_ID, mlp_weights=None,
-          features_out=None, steps_out=None, groups=0, pass_cycles_out=None):
-    f = (ORB_NONINDUCED if noninduced else 0) | (ORB_TIMING if timing else 0)
+          features_out=None, steps_out=None, groups=0, pass_cycles_out=None, relabel=False):
+    f = (ORB_NONINDUCED if noninduced else 0) | (ORB_TIMING if timing else 0) | \
+        (ORB_RELABEL if relabel else 0)
     g = GROUPS[groups] if isinstance(groups, str) else int(groups)
     return _Opts(f, num_wg, schedule, g, _ptr(mlp_weights), _ptr(features_out), _ptr(steps_out),
                  _ptr(pass_cycles_out))
 
 
 def workspace_bytes(row_ptr, col_idx, k_max=5, noninduced=False, num_wg=0, stream=None,
-                    groups="auto") -> int:
+                    groups="auto", relabel=False) -> int:
     rp, ci = _dev_csr(row_ptr, col_idx)
     n = rp.numel() - 1
     m = int(rp[-1].item()) // 2 if n >= 0 else 0
     out = ctypes.c_uint64(0)
-    o = _opts(noninduced, False, num_wg, groups=groups)
+    o = _opts(noninduced, False, num_wg, groups=groups, relabel=relabel)
     st = _lib.orbit_workspace_query(ctypes.c_void_p(rp.data_ptr()), ctypes.c_void_p(ci.data_ptr()),
                                     n, m, k_max, _stream_ptr(stream), ctypes.byref(o),
                                     ctypes.byref(out))
@@ -158,13 +160,14 @@ class Counter:
 
     def __init__(self, row_ptr, col_idx, k_max=5, noninduced=False, num_wg=0, stream=None,
                  schedule="id", mlp_weights=None, features_out=None, steps_out=None,
-                 groups="auto", pass_cycles_out=None):
+                 groups="auto", pass_cycles_out=None, relabel=False):
         """schedule: "id", "static" or "mlp" (source order of the per-source
         kernels; needs mlp_weights, a float32 device tensor of MLP_PARAMS
         values, for "mlp").  features_out (float32 [n, 3]) and steps_out
         (int64 [n], uint64 bits) receive the cost features and per-source
         pair-sweep step counts on every run when given; pass_cycles_out (int64
-        [4]) accumulates the pair sweep's per-pass clock cycles."""
+        [4]) accumulates the pair sweep's per-pass clock cycles.  relabel=True
+        counts on a copy renumbered heaviest degree class first (ORB_RELABEL)."""
         import torch
         self.rp, self.ci = _dev_csr(row_ptr, col_idx)
         self.n = self.rp.numel() - 1
@@ -175,13 +178,14 @@ class Counter:
             raise OrbError(-1, "k_max")
         sched = SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule)
         extra = dict(schedule=sched, mlp_weights=mlp_weights, features_out=features_out,
-                     steps_out=steps_out, groups=groups, pass_cycles_out=pass_cycles_out)
+                     steps_out=steps_out, groups=groups, pass_cycles_out=pass_cycles_out,
+                     relabel=relabel)
         self._keep = (mlp_weights, features_out, steps_out, pass_cycles_out)
         self.opts = _opts(noninduced, False, num_wg, **extra)
         self.topts = _opts(noninduced, True, num_wg, **extra)
         self.stream = stream
         self.ws_bytes = workspace_bytes(self.rp, self.ci, k_max, noninduced, num_wg, stream,
-                                        groups=groups)
+                                        groups=groups, relabel=relabel)
         self.ws = torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8, device=self.rp.device)
         self.out = torch.empty((max(self.n, 1), self.K), dtype=torch.int64, device=self.rp.device)
 
@@ -198,9 +202,10 @@ class Counter:
         return self.out[: self.n]
 
 
-def count(row_ptr, col_idx, k_max=5, noninduced=False, num_wg=0, groups="auto") -> np.ndarray:
+def count(row_ptr, col_idx, k_max=5, noninduced=False, num_wg=0, groups="auto",
+          relabel=False) -> np.ndarray:
     """uint64[n, K] orbit counts (induced unless noninduced=True)."""
-    c = Counter(row_ptr, col_idx, k_max, noninduced, num_wg, groups=groups)
+    c = Counter(row_ptr, col_idx, k_max, noninduced, num_wg, groups=groups, relabel=relabel)
     return c.run().cpu().numpy().view(np.uint64)
 
 

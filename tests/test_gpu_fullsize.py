@@ -108,3 +108,11 @@ def test_relabelled_graph_gives_permuted_counts(setup):
     torch.cuda.empty_cache()
     bad = np.flatnonzero((I2[perm] != I).any(axis=1))
     assert bad.size == 0, f"{bad.size} vertices differ, first {bad[:5]}"
+    # the library's own renumbering (heaviest degree class first) on the
+    # permuted graph: the same counts under the caller's ids
+    c = orbit.Counter(rp2, ci2, 5, schedule="mlp", mlp_weights=w, relabel=True)
+    I3 = c.run().cpu().numpy().view(U)
+    del c
+    torch.cuda.empty_cache()
+    bad = np.flatnonzero((I3 != I2).any(axis=1))
+    assert bad.size == 0, f"relabelled: {bad.size} vertices differ, first {bad[:5]}"

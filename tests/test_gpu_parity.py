@@ -235,3 +235,39 @@ def test_execution_groups(orbit, groups):
                                       oracle.induced_counts(rp, ci, threads=8))
         np.testing.assert_array_equal(orbit.count(rp, ci, 5, noninduced=True, groups=groups),
                                       oracle.noninduced_counts(rp, ci, threads=8))
+
+
+def test_relabelled_counting(orbit):
+    """ORB_RELABEL: counting on the renumbered copy gives the caller's counts
+    (rows of up to 64 sorted in registers, up to 4096 in LDS, longer ones by
+    bitmap: the books of 300 and 5000 pages have such rows)."""
+    graphs = [gg.relabel(*gg.chung_lu(800, 8.0, 2.1, 120.0, 3200, 71), 9),
+              gg.barabasi_albert(200, 3, 72), gg.erdos_renyi(40, 0.4, 73), gg.complete(12)]
+    for i, (rp, ci) in enumerate(graphs):
+        _say("relabel graph", i)
+        np.testing.assert_array_equal(orbit.count(rp, ci, 5, relabel=True),
+                                      oracle.induced_counts(rp, ci, threads=8))
+        np.testing.assert_array_equal(orbit.count(rp, ci, 5, noninduced=True, relabel=True),
+                                      oracle.noninduced_counts(rp, ci, threads=8))
+    for k in (300, 5000):
+        _say("relabel book", k)
+        rp, ci = gg.relabel(*_book(k), 5)
+        perm = np.random.Generator(np.random.PCG64(5)).permutation(k + 2)
+        got = orbit.count(rp, ci, 5, relabel=True)
+        np.testing.assert_array_equal(got[perm], _book_counts(k))
+    rp, ci = gg.erdos_renyi(30, 0.3, 74)
+    np.testing.assert_array_equal(orbit.count(rp, ci, 4, relabel=True),
+                                  oracle.induced_counts(rp, ci, kmax=4)[:, :15])
+
+
+def test_relabel_argument_errors(orbit):
+    import torch
+    rp, ci = gg.complete(6)
+    feat = torch.empty((6, 3), dtype=torch.float32, device="cuda")
+    with pytest.raises(orbit.OrbError):
+        orbit.Counter(rp, ci, 5, relabel=True, features_out=feat).run()
+    vptr, brp, bci = gg.batch_small(4, 3, nmin=5, nmax=8)
+    with pytest.raises(orbit.OrbError):
+        c = orbit.BatchCounter(vptr, brp, bci, 5)
+        c.opts.flags |= orbit.ORB_RELABEL
+        c.run()
