@@ -45,7 +45,7 @@ __global__ void k_vert0(const u32 *rp, const u32 *ci, const u32 *deg, const u32 
 // Theorem 5vertexorbit orbits 25, 26, 29, 32, 43, 46, 48, 52, 53, 54, 59,
 // 61, 65).  Each triangle is visited from the slot (u,v) with v < x.
 template <int G>
-__global__ void k_trisweep(const u32 *rp, const u32 *ci, const u32 *src, const u32 *rev,
+__global__ void k_trisweep(const u32 *rp, const u32 *ci, const u32 *rev,
                            const u32 *deg, const u32 *T, const u64 *tl_ptr, const uint2 *tl,
                            const u64 *Tv, const u64 *N1, const u64 *E7, const u64 *E9,
                            const u64 *C4e, const u64 *K4e, u32 n, u64 *ni) {

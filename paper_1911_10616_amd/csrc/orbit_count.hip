@@ -717,7 +717,7 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
                                              unsigned char *scratch, u64 stride, u32 *work,
                                              const u32 *order, u32 mapn, const u32 *gbase,
                                              u32 kl, u64 *steps, u64 *pass_cycles, u64 *Q,
-                                             u64 *ni, u64 *vacc) {
+                                             u64 *vacc) {
     __shared__ u32 sh_q_[GP::per_wg][3], sh_nt_[GP::per_wg], sh_next_[GP::per_wg];
     u32 *sh_q = sh_q_[GP::id()];
     if (GP::rank() == 0) { sh_q[0] = 0; sh_q[1] = 0; }
@@ -1013,8 +1013,8 @@ __device__ inline void hset_clear(u32 *hs, u32 k, const u64 *out_ptr, const u32 
 template <class GP>
 __global__ void __launch_bounds__(WG) k_c5(const u32 *rp, const u32 *ci, const u64 *key,
                                           const u64 *out_ptr, const u32 *out_nbr,
-                                          const u32 *out_slot, const u32 *Tin, const u32 *Tmid,
-                                          u32 n, unsigned char *scratch, u64 stride, u32 *work,
+                                          const u32 *Tin, const u32 *Tmid, u32 n,
+                                          unsigned char *scratch, u64 stride, u32 *work,
                                           const u32 *order, u32 mapn, const u32 *gbase,
                                           u64 *steps, u64 *cacc) {
     __shared__ u32 sh_q_[GP::per_wg][3], sh_nt_[GP::per_wg], sh_next_[GP::per_wg];

@@ -303,10 +303,6 @@ int scan(const T *in, u64 len, u64 *out, u64 *bsum, DevState *st, hipStream_t s)
     return ORB_OK;
 }
 
-struct Host {
-    DevState st;
-};
-
 int read_state(DevState *d, DevState *h, hipStream_t s) {
     HCHK(hipMemcpyAsync(h, d, sizeof(DevState), hipMemcpyDeviceToHost, s));
     HCHK(hipStreamSynchronize(s));
@@ -666,8 +662,8 @@ int count_impl(const u32 *rp, const u32 *ci, u32 n, u64 m, const u64 *vptr, u32 
         tm.mark("cliques");
         if (ntri) {
             WITH_GROUP(gsz, k_trisweep<GG><<<grid_for((u64)n * GG, WG), WG, 0, s>>>(
-                                rp, ci, src, rev, deg, T, tlptr, tl, Tv, N1, E7, E9, C4e, K4e,
-                                n, ni));
+                                rp, ci, rev, deg, T, tlptr, tl, Tv, N1, E7, E9, C4e, K4e, n,
+                                ni));
             HCHK(hipGetLastError());
         }
         tm.mark("trisweep");
@@ -687,14 +683,13 @@ int count_impl(const u32 *rp, const u32 *ci, u32 n, u64 m, const u64 *vptr, u32 
         tm.mark("zero_pairs");
         WITH_GP(wave_groups, k_pairs<GPT><<<L.nwg, WG, pair_lds, s>>>(rp, ci, src, rev, deg, T, tlptr, tl, n, scratch, L.stride,
                                      work + wi++, order, mapn, gbase, pair_kl, steps_out,
-                                     opts ? (u64 *)opts->pass_cycles_out : nullptr, Q, ni,
-                                     vacc));
+                                     opts ? (u64 *)opts->pass_cycles_out : nullptr, Q, vacc));
         HCHK(hipGetLastError());
         tm.mark("pairs");
         rc = zero_scratch(2, mapn, scratch, L, grp5, s);
         if (rc) return rc;
         tm.mark("zero_c5");
-        WITH_GP(wave_groups, k_c5<GPT><<<c5_wg, WG, 0, s>>>(rp, ci, key, outptr, outnbr, outslot, Tin, Tmid, n, scratch,
+        WITH_GP(wave_groups, k_c5<GPT><<<c5_wg, WG, 0, s>>>(rp, ci, key, outptr, outnbr, Tin, Tmid, n, scratch,
                                   L.stride, work + wi++, order, mapn, gbase, steps_out, cacc));
         HCHK(hipGetLastError());
         tm.mark("c5");
