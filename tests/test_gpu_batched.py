@@ -183,3 +183,36 @@ def test_full_batch_sampled_graphs_against_oracle(orbit):
         np.testing.assert_array_equal(got[a:b], oracle.induced_counts(*_graph(vptr, rp, ci, g),
                                                                      threads=8),
                                       err_msg=f"graph {g}")
+
+
+def test_plan_options(orbit):
+    """Plans of a non-induced count, of k_max = 4, and of a relabelled count
+    replay to the eager counts; the autotuner also works on one graph."""
+    import torch
+    rp, ci = gg.relabel(*gg.chung_lu(1500, 8.0, 2.1, 150.0, 6000, 109), 3)
+    for kw in (dict(noninduced=True), dict(k_max=4), dict(relabel=True)):
+        k_max = kw.pop("k_max", 5)
+        c = orbit.Counter(rp, ci, k_max, **kw)
+        ref = c.run().cpu().numpy().copy()
+        plan = orbit.Plan(c)
+        for _ in range(2):
+            c.out.fill_(-1)
+            got = plan.launch()
+            plan.status()
+            np.testing.assert_array_equal(got.cpu().numpy(), ref, err_msg=str(kw))
+        plan.close()
+    c = orbit.Counter(rp, ci, 5)
+    ref = c.run().cpu().numpy().copy()
+    cand = (ctypes.c_uint32 * 2)(256, 512)
+    best = orbit._Opts()
+    ms = ctypes.c_float(0)
+    base = orbit._opts()
+    st = orbit._lib.orbit_autotune(None, 0, ctypes.c_void_p(c.rp.data_ptr()),
+                                   ctypes.c_void_p(c.ci.data_ptr()), c.n, c.m, 5,
+                                   ctypes.c_void_p(c.out.data_ptr()),
+                                   ctypes.c_void_p(c.ws.data_ptr()), c.ws_bytes, None,
+                                   ctypes.byref(base), cand, 2, ctypes.byref(best),
+                                   ctypes.byref(ms))
+    assert st == 0 and best.num_wg in (256, 512) and ms.value > 0
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(c.out[: c.n].cpu().numpy(), ref)
