@@ -431,14 +431,24 @@ __host__ __device__ inline u64 clique_lds_words(u32 d) {
     return 2ull * d + 2ull * d * ((d + 63) / 64) + (d + 1) / 2;
 }
 
-__device__ inline u64 tri_find(u64 arc, u32 z, const u64 *tri_ptr, const u32 *tri_c,
-                               DevState *st) {
-    u64 b = tri_ptr[arc];
-    u32 len = (u32)(tri_ptr[arc + 1] - b);
-    u32 i = bfind(tri_c + b, len, z);
-    if (i == UNSET) { atomicOr(&st->err, ERRB_INTERNAL); return b; }
-    return b + i;
-}
+// Forward cursor over one triangle list: the keys it is asked for increase, so each search
+// covers only the entries after the previous hit.
+struct TriCursor {
+    u64 base;
+    u32 len;
+    __device__ void open(u64 arc, const u64 *tri_ptr) {
+        base = tri_ptr[arc];
+        len = (u32)(tri_ptr[arc + 1] - base);
+    }
+    __device__ u64 find(u32 z, const u32 *tri_c, DevState *st) {
+        u32 i = bfind(tri_c + base, len, z);
+        if (i == UNSET) { atomicOr(&st->err, ERRB_INTERNAL); return base; }
+        const u64 p = base + i;
+        base = p + 1;
+        len -= i + 1;
+        return p;
+    }
+};
 __device__ inline u64 arc_find(u32 x, u32 y, const u64 *out_ptr, const u32 *out_nbr,
                                DevState *st) {
     u64 b = out_ptr[x];
@@ -539,15 +549,21 @@ __global__ void __launch_bounds__(WG) k_clique(int pass, u32 n, const u32 *rev,
                     tot += k;
                 }
                 const u32 b = nbr[i];
+                // the apexes d come in increasing order, so the list of (b,c) is walked forward
+                TriCursor cbc;
+                bool open = false;
                 for (u32 w = 0; w < W; w++) {
                     u64 msk = oi[w] & oj[w];
                     while (msk) {
                         u32 l = w * 64 + __ffsll((long long)msk) - 1;
                         msk &= msk - 1;
                         u32 d = nbr[l];
+                        if (!open) {
+                            cbc.open(arc_find(b, c, out_ptr, out_nbr, st), tri_ptr);
+                            open = true;
+                        }
                         // the triangle (b,c,d) gets this 4-clique as an apex a
-                        u64 arc = arc_find(b, c, out_ptr, out_nbr, st);
-                        atomicAdd(&K4t[tri_find(arc, d, tri_ptr, tri_c, st)], 1u);
+                        atomicAdd(&K4t[cbc.find(d, tri_c, st)], 1u);
                         const u64 *ol = outm + (u64)l * W;
                         u32 c5 = 0;
                         for (u32 w2 = 0; w2 < W; w2++) c5 += __popcll(oi[w2] & oj[w2] & ol[w2]);
@@ -570,16 +586,24 @@ __global__ void __launch_bounds__(WG) k_clique(int pass, u32 n, const u32 *rev,
             } else {
                 const u32 b = nbr[i];
                 const u64 kt_abc = (u64)K4t[r];
+                // lists of (b,c), (a,c) and (a,b), each walked forward over increasing d
+                TriCursor cbc, cac, cab;
+                bool open = false;
                 for (u32 w = 0; w < W; w++) {
                     u64 msk = oi[w] & oj[w];
                     while (msk) {
                         u32 l = w * 64 + __ffsll((long long)msk) - 1;
                         msk &= msk - 1;
                         u32 d = nbr[l];
-                        u64 arc_bc = arc_find(b, c, out_ptr, out_nbr, st);
-                        tot += (u64)K4t[tri_find(arc_bc, d, tri_ptr, tri_c, st)] - 1;
-                        atomicAdd(&acc[i], (u64)K4t[tri_find(pa + j, d, tri_ptr, tri_c, st)] - 1);
-                        atomicAdd(&acc[j], (u64)K4t[tri_find(pa + i, d, tri_ptr, tri_c, st)] - 1);
+                        if (!open) {
+                            cbc.open(arc_find(b, c, out_ptr, out_nbr, st), tri_ptr);
+                            cac.open(pa + j, tri_ptr);
+                            cab.open(pa + i, tri_ptr);
+                            open = true;
+                        }
+                        tot += (u64)K4t[cbc.find(d, tri_c, st)] - 1;
+                        atomicAdd(&acc[i], (u64)K4t[cac.find(d, tri_c, st)] - 1);
+                        atomicAdd(&acc[j], (u64)K4t[cab.find(d, tri_c, st)] - 1);
                         atomicAdd(&acc[l], kt_abc - 1);
                     }
                 }
