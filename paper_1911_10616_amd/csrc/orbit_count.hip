@@ -506,7 +506,11 @@ __global__ void __launch_bounds__(WG) k_clique(int pass, u32 n, const u32 *rev,
             acc[i] = 0;
             acc5[i] = 0;
         }
-        for (u32 i = GP::rank(); i < D * W; i += GP::size) { und[i] = 0; outm[i] = 0; }
+        // the undirected rows serve the 4-clique popcounts of pass 1 only
+        for (u32 i = GP::rank(); i < D * W; i += GP::size) {
+            outm[i] = 0;
+            if (pass == 1) und[i] = 0;
+        }
         if (GP::rank() == 0) sh_next = 0;
         GP::sync();
         wave_loop(&sh_next, D, [&](u32 i) {
@@ -515,8 +519,10 @@ __global__ void __launch_bounds__(WG) k_clique(int pass, u32 n, const u32 *rev,
                 u32 j = bfind(nbr, D, out_nbr[q]);
                 if (j != UNSET) {
                     atomicOr(&outm[(u64)i * W + j / 64], 1ull << (j % 64));
-                    atomicOr(&und[(u64)i * W + j / 64], 1ull << (j % 64));
-                    atomicOr(&und[(u64)j * W + i / 64], 1ull << (i % 64));
+                    if (pass == 1) {
+                        atomicOr(&und[(u64)i * W + j / 64], 1ull << (j % 64));
+                        atomicOr(&und[(u64)j * W + i / 64], 1ull << (i % 64));
+                    }
                 }
             }
         });
