@@ -136,10 +136,24 @@ int orbit_workspace_query(const uint32_t *row_ptr, const uint32_t *col_idx, uint
 /* Full form: uses only the caller's workspace (device memory of ws_bytes
  * bytes, 256-byte aligned); allocates no device memory.  If the workspace
  * is too small it returns ORB_E_WORKSPACE and, when ws_required is not
- * NULL, stores the size it needs there.  opts may be NULL. */
+ * NULL, stores the size it needs there.  opts may be NULL.
+ *
+ * overflow_flags (DEVICE, n bytes, nullable): the paper does not discuss
+ * integer width; counts are exact modulo 2^64.  When given, byte u is set
+ * to 1 when an upper bound of u's non-induced counts reaches 2^63, else 0,
+ * so every row whose flag is 0 is exact (induced counts never exceed the
+ * non-induced ones).  The bound, evaluated in fp64: a non-induced copy of a
+ * k-vertex pattern at u is a connected k-vertex subgraph containing u; it
+ * contains a spanning tree, and at most 2^(C(k,2)-k+1) such subgraphs share
+ * one tree, while the number of k-vertex trees containing u is at most the
+ * sum, over the rooted tree shapes with k vertices, of the homomorphism
+ * counts into G with the root at u (nested neighbour-degree sums) divided
+ * by the shape's root-fixing automorphisms.  Flagged rows still hold the
+ * counts modulo 2^64. */
 int orbit_count_ex(const uint32_t *row_ptr, const uint32_t *col_idx, uint32_t n, uint64_t m,
-                   int k_max, uint64_t *counts, void *workspace, uint64_t ws_bytes,
-                   uint64_t *ws_required, void *stream, const orb_opts *opts);
+                   int k_max, uint64_t *counts, uint8_t *overflow_flags, void *workspace,
+                   uint64_t ws_bytes, uint64_t *ws_required, void *stream,
+                   const orb_opts *opts);
 
 /* ---- many small graphs in one call.
  * The batch is the disjoint union of num_graphs graphs stored as one CSR

@@ -16,6 +16,10 @@ Parity status of each function (what pins it is listed in the tests):
                       brute-force injective maps, Fig. A)
   rooted_counts       pinned against induced_counts (same definition)
   transform_matrix    pinned against Fig. A (with the row-5 erratum)
+  overflow_flags      the overflow reading of integer width (the paper is
+                      silent on it): pinned by brute-force homomorphism
+                      counts of every rooted tree shape on tiny graphs and by
+                      the bound holding over every non-induced count
 """
 from __future__ import annotations
 
@@ -202,3 +206,70 @@ def _pattern_edges(h):
             return [(i, j) for j in range(1, k) for i in range(j)
                     if mask >> pair_index(i, j) & 1]
     raise RuntimeError("pattern not found in LUT")
+
+
+# ------------------------------------------------------------ overflow flags
+# The paper never discusses integer width.  Reading: counts are exact
+# modulo 2^64, and a row is flagged when an upper bound of its non-induced
+# counts reaches 2^63.  A non-induced copy of a connected k-vertex pattern at
+# u is a connected k-vertex subgraph containing u; it holds a spanning tree,
+# and at most 2^(C(k,2)-(k-1)) subgraphs of one vertex set share that tree.
+# The trees with k vertices containing u number at most
+# sum over rooted shapes tau of hom(tau, G; root -> u) / |Aut_root(tau)|.
+ROOTED_TREES = {
+    # shape name: (vertices, root-fixing automorphisms); a shape is written
+    # as the tuple of its root's child subtrees
+    3: [("P3_end", 1), ("P3_mid", 2)],
+    4: [("P4_end", 1), ("S3_leaf", 2), ("P4_inner", 1), ("S3_centre", 6)],
+    5: [("P5_end", 1), ("fork_tip", 2), ("chair_end", 1), ("S4_leaf", 6),
+        ("P5_second", 1), ("fork_second", 2), ("P5_centre", 2), ("chair_deg3", 2),
+        ("S4_centre", 24)],
+}
+
+
+def rooted_tree_homs(row_ptr, col_idx):
+    """dict shape -> float64[n] of hom(tau, G; root -> u), by the nested
+    neighbour sums of the degrees (child subtrees multiply, a child's count
+    is summed over the neighbours it can map to)."""
+    rp = np.asarray(row_ptr, np.int64)
+    ci = np.asarray(col_idx, np.int64)
+    n = rp.size - 1
+    d = np.diff(rp).astype(np.float64)
+    src = np.repeat(np.arange(n), np.diff(rp))
+
+    def nsum(x):  # sum over neighbours
+        return np.bincount(src, weights=x[ci], minlength=n) if ci.size else np.zeros(n)
+
+    s1 = nsum(d)            # root - v - (leaf)
+    q1 = nsum(d * d)        # root - v with two leaves
+    c1 = nsum(d ** 3)       # root - v with three leaves
+    s2 = nsum(s1)           # root - v - w - (leaf)
+    q2 = nsum(q1)           # root - v - w with two leaves
+    r1 = nsum(d * s1)       # root - v, v with a leaf and a 2-path
+    s3 = nsum(s2)           # path of 5 from the root
+    return {
+        "P3_end": s1, "P3_mid": d * d,
+        "P4_end": s2, "S3_leaf": q1, "P4_inner": s1 * d, "S3_centre": d ** 3,
+        "P5_end": s3, "fork_tip": q2, "chair_end": r1, "S4_leaf": c1,
+        "P5_second": s2 * d, "fork_second": q1 * d, "P5_centre": s1 * s1,
+        "chair_deg3": s1 * d * d, "S4_centre": d ** 4,
+    }
+
+
+def count_bound(row_ptr, col_idx):
+    """float64[n]: upper bound of every non-induced count of each vertex."""
+    h = rooted_tree_homs(row_ptr, col_idx)
+    d = np.diff(np.asarray(row_ptr, np.int64)).astype(np.float64)
+    tot = d.copy()
+    for k, extra in ((3, 2.0), (4, 8.0), (5, 64.0)):
+        b = np.zeros_like(d)
+        for name, aut in ROOTED_TREES[k]:
+            b += h[name] / aut
+        tot += extra * b
+    return tot
+
+
+def overflow_flags(row_ptr, col_idx) -> np.ndarray:
+    """uint8[n]: 1 where the count bound reaches 2^63 (less a 1e-9 relative
+    margin for the rounding of the fp64 sums)."""
+    return (count_bound(row_ptr, col_idx) >= 2.0 ** 63 * (1 - 1e-9)).astype(np.uint8)

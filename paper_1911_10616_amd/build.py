@@ -1,4 +1,13 @@
-"""Build liborbit_hip.so (hipcc, gfx950) in-tree."""
+"""Build liborbit_hip.so (hipcc, gfx950) in-tree.
+
+Two builds of the same sources:
+* ``liborbit_hip.so`` -- the library;
+* ``liborbit_hip_tiles.so`` -- the same code with every LDS tile shrunk
+  (clique bit rows, pair-sweep wheel maps, the 5-cycle hash set, the long
+  triangle-list sort), so that graphs small enough for the CPU oracle take
+  the paths that only hubs of large graphs take in the library build.  Only
+  the tests load it.
+"""
 from __future__ import annotations
 
 import os
@@ -7,22 +16,35 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liborbit_hip.so")
+LIB_TILES = os.path.join(HERE, "liborbit_hip_tiles.so")
 SOURCES = ["orbit_lib.hip", "orbit_prep.hip", "orbit_count.hip", "orbit_combine.hip",
-           "orbit_common.h", "orbit_tables.h"]
+           "orbit_sched.hip", "orbit_common.h", "orbit_tables.h"]
+# tile sizes of the test build (each the smallest its kernel accepts or a
+# size a 40..120-vertex graph exceeds)
+SMALL_TILES = {"CLQ_LDS_D": 16, "PAIR_KMAP_LDS": 32, "C5_HSET": 64, "TL_SORT_LDS": 128,
+               "PAIR_HUB_LDS": 64}
 
 
-def hipcc_command(out: str = LIB):
-    return ["hipcc", "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",
-            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-            "-I", os.path.join(HERE, "..", "include"),
-            "-o", out, os.path.join(CSRC, "orbit_lib.hip")]
+def hipcc_command(out: str = LIB, defines=None):
+    cmd = ["hipcc", "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           "-I", os.path.join(HERE, "..", "include")]
+    for k, v in (defines or {}).items():
+        cmd.append(f"-D{k}={v}")
+    return cmd + ["-o", out, os.path.join(CSRC, "orbit_lib.hip")]
+
+
+def _build_one(out, defines=None):
+    tmp = out + ".tmp"
+    subprocess.check_call(hipcc_command(tmp, defines))
+    os.replace(tmp, out)
+    return out
 
 
 def build() -> str:
-    """Compile the HIP library (always recompiles)."""
-    tmp = LIB + ".tmp"
-    subprocess.check_call(hipcc_command(tmp))
-    os.replace(tmp, LIB)
+    """Compile both builds (always recompiles); returns the library's path."""
+    _build_one(LIB)
+    _build_one(LIB_TILES, SMALL_TILES)
     return LIB
 
 

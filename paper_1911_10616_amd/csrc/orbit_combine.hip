@@ -338,3 +338,63 @@ __global__ void k_stats(const u32 *src, const u32 *ci, const u32 *deg, const u32
         atomic_add_u64(&st->diamonds, d);
     }
 }
+
+// ---- overflow flags.  Counts are exact modulo 2^64; a row is certainly
+// exact when every non-induced count of the vertex is below 2^63.  Bound:
+// a non-induced copy of a k-vertex pattern at u is a connected k-vertex
+// subgraph containing u; it contains a spanning tree, and at most
+// 2^(C(k,2)-k+1) subgraphs on one vertex set share a tree (64, 8, 2 for
+// k = 5, 4, 3).  The k-vertex trees containing u number at most the sum over
+// the rooted tree shapes with k vertices of hom(shape, G; root -> u) divided
+// by the shape's root-fixing automorphisms, and those homomorphism counts
+// are nested neighbour sums of degrees:
+//   pass 0: s1 = sum_{v~u} d(v),  q1 = sum d(v)^2,  c1 = sum d(v)^3
+//   pass 1: s2 = sum_{v~u} s1(v), q2 = sum q1(v),   r1 = sum d(v) s1(v)
+//   pass 2: s3 = sum_{v~u} s2(v), then
+//     B3 = s1 + d^2/2
+//     B4 = s2 + q1/2 + d s1 + d^3/6
+//     B5 = s3 + q2/2 + r1 + c1/6 + d s2 + d q1/2 + s1^2/2 + d^2 s1/2 + d^4/24
+//   flag = 64 B5 + 8 B4 + 2 B3 + d >= 2^63 (less a relative margin that
+//   covers the fp64 rounding of the sums).
+template <int G> __device__ inline double group_sum_f64(double v) {
+    for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
+    return v;
+}
+template <int G>
+__global__ void k_ovf(const u32 *rp, const u32 *ci, u32 n, int pass, double *a, double *b,
+                      unsigned char *flags) {
+    GROUP_LOOP(G, u, n) {
+        double x0 = 0, x1 = 0, x2 = 0;
+        for (u32 s = (u < n ? rp[u] : 0) + glane<G>(); s < (u < n ? rp[u + 1] : 0); s += G) {
+            const u32 v = ci[s];
+            const double dv = (double)(rp[v + 1] - rp[v]);
+            if (pass == 0) {
+                x0 += dv; x1 += dv * dv; x2 += dv * dv * dv;
+            } else if (pass == 1) {
+                const double s1v = a[(u64)v * 3];
+                x0 += s1v; x1 += a[(u64)v * 3 + 1]; x2 += dv * s1v;
+            } else {
+                x0 += b[(u64)v * 3];
+            }
+        }
+        x0 = group_sum_f64<G>(x0);
+        x1 = group_sum_f64<G>(x1);
+        x2 = group_sum_f64<G>(x2);
+        if (glane<G>() != 0 || u >= n) continue;
+        if (pass == 0) {
+            a[u * 3] = x0; a[u * 3 + 1] = x1; a[u * 3 + 2] = x2;
+        } else if (pass == 1) {
+            b[u * 3] = x0; b[u * 3 + 1] = x1; b[u * 3 + 2] = x2;
+        } else {
+            const double d = (double)(rp[u + 1] - rp[u]);
+            const double s1 = a[u * 3], q1 = a[u * 3 + 1], c1 = a[u * 3 + 2];
+            const double s2 = b[u * 3], q2 = b[u * 3 + 1], r1 = b[u * 3 + 2], s3 = x0;
+            const double B3 = s1 + d * d / 2;
+            const double B4 = s2 + q1 / 2 + d * s1 + d * d * d / 6;
+            const double B5 = s3 + q2 / 2 + r1 + c1 / 6 + d * s2 + d * q1 / 2 + s1 * s1 / 2 +
+                              d * d * s1 / 2 + d * d * d * d / 24;
+            const double bound = 64 * B5 + 8 * B4 + 2 * B3 + d;
+            flags[u] = bound >= 9223372036854775808.0 * (1.0 - 1e-9) ? 1 : 0;
+        }
+    }
+}

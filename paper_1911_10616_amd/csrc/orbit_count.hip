@@ -32,9 +32,12 @@ __global__ void k_tri_count(const u32 *src, const u64 *out_ptr, const u32 *out_n
 
 // Triangle records, grouped by owner arc (a->b) and sorted by c:
 // tri_c = c, tri_sab/sac/sbc = slots of (a,b), (a,c), (b,c).
+// Writes nothing once an error is recorded (a replayed plan whose triangle
+// count differs from the planned one must not write past its buffers).
 __global__ void k_tri_fill(const u32 *src, const u64 *out_ptr, const u32 *out_nbr,
                            const u32 *out_slot, u64 m, const u64 *tri_ptr, u32 *tri_c,
-                           u32 *tri_sab, u32 *tri_sac, u32 *tri_sbc) {
+                           u32 *tri_sab, u32 *tri_sac, u32 *tri_sbc, const DevState *st) {
+    if (st->err) return;
     for (u64 p = GTID; p < m; p += GSTRIDE) {
         u32 a = arc_owner_of(src, out_slot, p), b = out_nbr[p];
         u64 i = out_ptr[a], ie = out_ptr[a + 1], j = out_ptr[b], je = out_ptr[b + 1];
@@ -104,6 +107,8 @@ __global__ void k_tl_fill(const u32 *src, const u32 *ci, const u32 *rev, u64 ntr
 #ifndef TL_SORT_LDS
 #define TL_SORT_LDS 4096
 #endif
+static_assert(TL_SORT_LDS >= 128 && (TL_SORT_LDS & (TL_SORT_LDS - 1)) == 0,
+              "TL_SORT_LDS: a power of two >= 128");
 __device__ inline u64 tl_key(uint2 e) { return ((u64)e.x << 32) | e.y; }
 __device__ inline uint2 tl_unkey(u64 k) { return make_uint2((u32)(k >> 32), (u32)k); }
 
@@ -140,9 +145,11 @@ __global__ void k_tl_sort_small(const u32 *src, const u32 *ci, const u32 *T, con
 __global__ void __launch_bounds__(WG) k_tl_sort_wg(const u32 *rp, const u32 *src, const u32 *ci,
                                                   const u32 *T, const u64 *tl_ptr, uint2 *tl,
                                                   const u32 *queue, const u32 *qlen,
-                                                  unsigned char *scratch, u64 stride, u32 mapn) {
+                                                  unsigned char *scratch, u64 stride, u32 mapn,
+                                                  const DevState *st) {
     __shared__ u64 sk[TL_SORT_LDS];
     __shared__ u32 part[WG];
+    if (st->err) return;
     u32 *oth = (u32 *)(scratch + (u64)blockIdx.x * stride);          // mapn entries
     u32 *bm = (u32 *)align256((unsigned char *)(oth + mapn));        // ceil(mapn/32) words
     const u32 cnt = *qlen;
@@ -295,18 +302,25 @@ struct GpWave {
 // takes GP::chunk consecutive entries per atomic on the shared counter (light
 // sources would otherwise serialise on it).  q[0..1] = the group's current
 // range of queue entries, q[2] = the source handed out; both start at 0.
+// Once an error is recorded (st->err) the queue reads as empty, so a
+// replayed plan whose sizes no longer match its buffers stops early.
 template <class GP>
-__device__ inline u32 next_source(u32 *counter, u32 *q, const u32 *order, u32 n) {
+__device__ inline u32 next_source(u32 *counter, u32 *q, const u32 *order, u32 n,
+                                  const DevState *st) {
     GP::sync();
     if (GP::rank() == 0) {
-        if (q[0] >= q[1]) {
-            const u32 i = atomicAdd(counter, GP::chunk);
-            q[0] = i;
-            q[1] = i < n ? (n - i < GP::chunk ? n : i + GP::chunk) : i;
+        if (__atomic_load_n(&st->err, __ATOMIC_RELAXED)) {
+            q[2] = n;
+        } else {
+            if (q[0] >= q[1]) {
+                const u32 i = atomicAdd(counter, GP::chunk);
+                q[0] = i;
+                q[1] = i < n ? (n - i < GP::chunk ? n : i + GP::chunk) : i;
+            }
+            const u32 i = q[0];
+            q[2] = i < q[1] ? (order ? order[i] : i) : n;
+            q[0] = i + 1;
         }
-        const u32 i = q[0];
-        q[2] = i < q[1] ? (order ? order[i] : i) : n;
-        q[0] = i + 1;
     }
     GP::sync();
     return q[2];
@@ -344,7 +358,8 @@ template <class GP>
 __global__ void __launch_bounds__(WG) k_c4(const u32 *rp, const u32 *ci, const u32 *rev,
                                           const u64 *key, u32 n, unsigned char *scratch,
                                           u64 stride, u32 *work, const u32 *order, u32 mapn,
-                                          const u32 *gbase, u64 *C4v, u64 *C4e) {
+                                          const u32 *gbase, u64 *C4v, u64 *C4e,
+                                          const DevState *st) {
     __shared__ u32 sh_q_[GP::per_wg][3], sh_nt_[GP::per_wg], sh_next_[GP::per_wg];
     u32 *sh_q = sh_q_[GP::id()];
     if (GP::rank() == 0) { sh_q[0] = 0; sh_q[1] = 0; }
@@ -355,7 +370,7 @@ __global__ void __launch_bounds__(WG) k_c4(const u32 *rp, const u32 *ci, const u
     u32 *cnt = (u32 *)base;
     u32 *touched = (u32 *)align256((unsigned char *)(cnt + mapn));
     for (;;) {
-        u32 x = next_source<GP>(work, sh_q, order, n);
+        u32 x = next_source<GP>(work, sh_q, order, n, st);
         if (x >= n) break;
         const u32 vb = gbase ? gbase[x] : 0;  // maps are indexed within x's graph
         const u64 kx = key[x];
@@ -424,8 +439,9 @@ __global__ void __launch_bounds__(WG) k_c4(const u32 *rp, const u32 *ci, const u
 //           lowest vertex precedes the triangle), 5-cliques (orbit 72).
 //   pass 2: orbit 70, sum over 4-cliques containing u of K4(opposite
 //           triangle) - 1 (Theorem 5vertexorbit), needing the final K4(t).
+#ifndef CLQ_LDS_D
 #define CLQ_LDS_D 384
-#define CLQ_LDS_W (CLQ_LDS_D / 64)
+#endif
 // u64 words of one execution group's LDS rows for out-degrees up to d
 __host__ __device__ inline u64 clique_lds_words(u32 d) {
     return 2ull * d + 2ull * d * ((d + 63) / 64) + (d + 1) / 2;
@@ -480,7 +496,7 @@ __global__ void __launch_bounds__(WG) k_clique(int pass, u32 n, const u32 *rev,
     u32 *l_nbr = (u32 *)(l_out + (u64)lds_d * lds_w);
     unsigned char *gbase = scratch + GP::global_id() * stride;
     for (;;) {
-        u32 a = next_source<GP>(work, sh_q, order, n);
+        u32 a = next_source<GP>(work, sh_q, order, n, st);
         if (a >= n) break;
         const u64 pa = out_ptr[a];
         const u32 D = (u32)(out_ptr[a + 1] - pa);
@@ -747,7 +763,7 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
                                              unsigned char *scratch, u64 stride, u32 *work,
                                              const u32 *order, u32 mapn, const u32 *gbase,
                                              u32 kl, u64 *steps, u64 *pass_cycles, u64 *Q,
-                                             u64 *vacc) {
+                                             u64 *vacc, const DevState *st) {
     __shared__ u32 sh_q_[GP::per_wg][3], sh_nt_[GP::per_wg], sh_next_[GP::per_wg];
     u32 *sh_q = sh_q_[GP::id()];
     if (GP::rank() == 0) { sh_q[0] = 0; sh_q[1] = 0; }
@@ -768,7 +784,7 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
     for (u32 i = threadIdx.x; i < WAVES_PER_WG * kl; i += WG) l_k0[i] = 0;
     __syncthreads();
     for (;;) {
-        const u32 a = next_source<GP>(work, sh_q, order, n);
+        const u32 a = next_source<GP>(work, sh_q, order, n, st);
         if (a >= n) break;
         const u32 vb = gbase ? gbase[a] : 0;  // maps are indexed within a's graph
         const u32 ba = rp[a], da = rp[a + 1] - ba;
@@ -995,8 +1011,17 @@ __device__ inline bool out_adjacent(u32 k, u32 i, const u64 *out_ptr, const u32 
 // Per-wave hash set of N+(k) in LDS (open addressing, keys id + 1, 0 =
 // empty), for the test "k -> i" of every directed 3-path through k; used
 // when d+(k) <= C5_HSET / 2, else a binary search in N+(k).
+#ifndef C5_HSET
 #define C5_HSET 1024
-__device__ inline u32 hset_slot(u32 key) { return (key * 2654435761u) >> 22; }
+#endif
+static_assert(C5_HSET >= 64 && (C5_HSET & (C5_HSET - 1)) == 0, "C5_HSET: a power of two >= 64");
+constexpr int c5_hset_bits() {
+    int b = 0;
+    while ((1 << b) < C5_HSET) b++;
+    return b;
+}
+// multiplicative hash onto the C5_HSET slots (the top bits of key * 2^32/phi)
+__device__ inline u32 hset_slot(u32 key) { return (key * 2654435761u) >> (32 - c5_hset_bits()); }
 __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_wave_barrier();
@@ -1046,7 +1071,7 @@ __global__ void __launch_bounds__(WG) k_c5(const u32 *rp, const u32 *ci, const u
                                           const u32 *Tin, const u32 *Tmid, u32 n,
                                           unsigned char *scratch, u64 stride, u32 *work,
                                           const u32 *order, u32 mapn, const u32 *gbase,
-                                          u64 *steps, u64 *cacc) {
+                                          u64 *steps, u64 *cacc, const DevState *st) {
     __shared__ u32 sh_q_[GP::per_wg][3], sh_nt_[GP::per_wg], sh_next_[GP::per_wg];
     u32 *sh_q = sh_q_[GP::id()];
     if (GP::rank() == 0) { sh_q[0] = 0; sh_q[1] = 0; }
@@ -1059,7 +1084,7 @@ __global__ void __launch_bounds__(WG) k_c5(const u32 *rp, const u32 *ci, const u
     __syncthreads();
     u32 *hs = l_hs[wave_in_wg()];
     for (;;) {
-        const u32 l = next_source<GP>(work, sh_q, order, n);
+        const u32 l = next_source<GP>(work, sh_q, order, n, st);
         if (l >= n) break;
         const u32 vb = gbase ? gbase[l] : 0;  // maps are indexed within l's graph
         const u32 bl = rp[l], dl = rp[l + 1] - bl;

@@ -160,7 +160,10 @@ void layout_phase2(Layout &L, u32 n, u32 mapn, u64 m, u64 ntri, u32 dmax, int k_
     L.nwg = nwg;
     L.per_wg = per_wg;
     L.stride = stride;
-    place(c, L.scratch, (u64)nwg * per_wg * stride);
+    // the overflow bound borrows the scratch for 6 doubles per vertex
+    u64 sbytes = (u64)nwg * per_wg * stride;
+    if (sbytes < 48ull * n + 256) sbytes = 48ull * n + 256;
+    place(c, L.scratch, sbytes);
     L.total = align_up(c, 256);
 }
 
@@ -357,6 +360,7 @@ int run_phase1(const u32 *rp, const u32 *ci, u32 n, u64 m, const u64 *vptr, u32 
     if (vptr) {
         gbase = at<u32>(ws, L.gbase);
         k_batch_index<<<grid_waves(B), WG, 0, s>>>(vptr, B, n, gbase, st);
+        if (cap) k_plan_guard<<<1, 64, 0, s>>>(st, 0, pl->gmax);
         HCHK(hipGetLastError());
         if (!cap) {
             rc = read_state(st, hs, s);
@@ -400,6 +404,7 @@ int run_phase1(const u32 *rp, const u32 *ci, u32 n, u64 m, const u64 *vptr, u32 
         }
         if (it > (int)(4u * (u64)n / 32u + 1000000)) return ORB_E_INTERNAL;
     }
+    if (cap) k_plan_guard<<<1, 64, 0, s>>>(st, 1, 0);
     k_rank_key<<<grid_for(n, WG), WG, 0, s>>>(rnd, n, key);
     tm.mark("peel");
 
@@ -412,6 +417,7 @@ int run_phase1(const u32 *rp, const u32 *ci, u32 n, u64 m, const u64 *vptr, u32 
         rc = scan<u32>(tcnt, m, triptr, bsum, st, s);
         if (rc) return rc;
         k_save_ntri<<<1, 64, 0, s>>>(st);
+        if (cap) k_plan_guard<<<1, 64, 0, s>>>(st, 2, pl->ntri);
     }
     HCHK(hipGetLastError());
     if (cap) {
@@ -484,7 +490,7 @@ int relabel_input(const u32 *rp, const u32 *ci, u32 n, u64 m, void *ws, const La
 }
 
 int count_impl(const u32 *rp, const u32 *ci, u32 n, u64 m, const u64 *vptr, u32 B, int k_max,
-               u64 *counts, void *ws,
+               u64 *counts, unsigned char *ovf, void *ws,
                u64 ws_bytes, u64 *ws_required, hipStream_t s, const orb_opts *opts,
                bool query_only, Plan *pl = nullptr) {
     const bool cap = pl && pl->capture;
@@ -510,6 +516,7 @@ int count_impl(const u32 *rp, const u32 *ci, u32 n, u64 m, const u64 *vptr, u32 
     DevState hs;
     memset(&hs, 0, sizeof hs);
     const u32 *orig = nullptr;  // relabelled vertex -> caller's vertex
+    const u32 *rp_in = rp, *ci_in = ci;  // the caller's graph
     if (relabel && n) {
         const u32 *nrp = nullptr, *nci = nullptr;
         int rc0 = relabel_input(rp, ci, n, m, ws, L, s, &hs, cap, &nrp, &nci);
@@ -580,6 +587,15 @@ int count_impl(const u32 *rp, const u32 *ci, u32 n, u64 m, const u64 *vptr, u32 
     rc = zero_u64(ni, (u64)ORB_NORB * n, s);
     if (rc) return rc;
     tm.mark("zero");
+    if (ovf) {  // overflow flags on the caller's graph (scratch is free until the list sorts)
+        double *oa = (double *)scratch, *ob = oa + 3ull * n;
+        const int g = group_size(n, m);
+        for (int pass = 0; pass < 3; pass++)
+            WITH_GROUP(g, k_ovf<GG><<<grid_for((u64)n * GG, WG), WG, 0, s>>>(rp_in, ci_in, n, pass,
+                                                                           oa, ob, ovf));
+        HCHK(hipGetLastError());
+        tm.mark("overflow");
+    }
 
     // schedule of the per-source kernels
     float *feat = (opts && opts->features_out) ? opts->features_out : at<float>(ws, L.feat);
@@ -613,7 +629,7 @@ int count_impl(const u32 *rp, const u32 *ci, u32 n, u64 m, const u64 *vptr, u32 
 
     if (ntri) {
         k_tri_fill<<<grid_for(m, WG), WG, 0, s>>>(src, outptr, outnbr, outslot, m, triptr, tri_c,
-                                                  tri_sab, tri_sac, tri_sbc);
+                                                  tri_sab, tri_sac, tri_sbc, st);
         k_tri_slots<<<grid_for(ntri, WG), WG, 0, s>>>(rev, ntri, tri_sab, tri_sac, tri_sbc, T, Tin,
                                                       Tmid);
         HCHK(hipGetLastError());
@@ -634,7 +650,7 @@ int count_impl(const u32 *rp, const u32 *ci, u32 n, u64 m, const u64 *vptr, u32 
             u32 *qlen = st->work + 15;
             k_tl_sort_small<<<grid_waves(M2), WG, 0, s>>>(src, ci, T, tlptr, tl, M2, tllen, qlen);
             k_tl_sort_wg<<<L.nwg, WG, 0, s>>>(rp, src, ci, T, tlptr, tl, tllen, qlen, scratch,
-                                              L.stride, mapn);
+                                              L.stride, mapn, st);
             HCHK(hipGetLastError());
         }
     }
@@ -650,7 +666,7 @@ int count_impl(const u32 *rp, const u32 *ci, u32 n, u64 m, const u64 *vptr, u32 
         if (rc) return rc;
         tm.mark("zero_c4");
         WITH_GP(wave_groups, k_c4<GPT><<<L.nwg, WG, 0, s>>>(rp, ci, rev, key, n, scratch, L.stride, work + wi++, order,
-                                  mapn, gbase, C4v, C4e));
+                                  mapn, gbase, C4v, C4e, st));
         HCHK(hipGetLastError());
         tm.mark("c4");
         if (ntri) {
@@ -683,14 +699,14 @@ int count_impl(const u32 *rp, const u32 *ci, u32 n, u64 m, const u64 *vptr, u32 
         tm.mark("zero_pairs");
         WITH_GP(wave_groups, k_pairs<GPT><<<L.nwg, WG, pair_lds, s>>>(rp, ci, src, rev, deg, T, tlptr, tl, n, scratch, L.stride,
                                      work + wi++, order, mapn, gbase, pair_kl, steps_out,
-                                     opts ? (u64 *)opts->pass_cycles_out : nullptr, Q, vacc));
+                                     opts ? (u64 *)opts->pass_cycles_out : nullptr, Q, vacc, st));
         HCHK(hipGetLastError());
         tm.mark("pairs");
         rc = zero_scratch(2, mapn, scratch, L, grp5, s);
         if (rc) return rc;
         tm.mark("zero_c5");
         WITH_GP(wave_groups, k_c5<GPT><<<c5_wg, WG, 0, s>>>(rp, ci, key, outptr, outnbr, Tin, Tmid, n, scratch,
-                                  L.stride, work + wi++, order, mapn, gbase, steps_out, cacc));
+                                  L.stride, work + wi++, order, mapn, gbase, steps_out, cacc, st));
         HCHK(hipGetLastError());
         tm.mark("c5");
     }
@@ -737,10 +753,11 @@ int orbit_num_orbits(int k_max) {
 }
 
 int orbit_count_ex(const uint32_t *row_ptr, const uint32_t *col_idx, uint32_t n, uint64_t m,
-                   int k_max, uint64_t *counts, void *workspace, uint64_t ws_bytes,
-                   uint64_t *ws_required, void *stream, const orb_opts *opts) {
-    return count_impl(row_ptr, col_idx, n, m, nullptr, 0, k_max, (u64 *)counts, workspace, ws_bytes,
-                      (u64 *)ws_required, (hipStream_t)stream, opts, false);
+                   int k_max, uint64_t *counts, uint8_t *overflow_flags, void *workspace,
+                   uint64_t ws_bytes, uint64_t *ws_required, void *stream,
+                   const orb_opts *opts) {
+    return count_impl(row_ptr, col_idx, n, m, nullptr, 0, k_max, (u64 *)counts, overflow_flags,
+                      workspace, ws_bytes, (u64 *)ws_required, (hipStream_t)stream, opts, false);
 }
 
 int orbit_workspace_query(const uint32_t *row_ptr, const uint32_t *col_idx, uint32_t n,
@@ -753,7 +770,7 @@ int orbit_workspace_query(const uint32_t *row_ptr, const uint32_t *col_idx, uint
     void *tmp = nullptr;
     if (hipMalloc(&tmp, L.p1_end) != hipSuccess) return ORB_E_DEVICE;
     u64 req = 0;
-    int rc = count_impl(row_ptr, col_idx, n, m, nullptr, 0, k_max, nullptr, tmp, L.p1_end, &req,
+    int rc = count_impl(row_ptr, col_idx, n, m, nullptr, 0, k_max, nullptr, nullptr, tmp, L.p1_end, &req,
                         (hipStream_t)stream, opts, true);
     (void)hipFree(tmp);
     if (rc) return rc;
@@ -768,8 +785,8 @@ int orbit_count(const uint32_t *row_ptr, const uint32_t *col_idx, uint32_t n, ui
     if (rc) return rc;
     void *ws = nullptr;
     if (hipMalloc(&ws, need ? need : 256) != hipSuccess) return ORB_E_DEVICE;
-    rc = orbit_count_ex(row_ptr, col_idx, n, m, k_max, counts, ws, need, nullptr, nullptr,
-                        nullptr);
+    rc = orbit_count_ex(row_ptr, col_idx, n, m, k_max, counts, nullptr, ws, need, nullptr,
+                        nullptr, nullptr);
     (void)hipFree(ws);
     return rc;
 }
@@ -780,7 +797,7 @@ int orbit_count_batched(const uint64_t *vptr, uint32_t num_graphs, const uint32_
                         uint64_t *ws_required, void *stream, const orb_opts *opts) {
     if (!vptr) return ORB_E_INVALID_ARG;
     return count_impl(row_ptr, col_idx, n, m, (const u64 *)vptr, num_graphs, k_max,
-                      (u64 *)counts, workspace, ws_bytes, (u64 *)ws_required,
+                      (u64 *)counts, nullptr, workspace, ws_bytes, (u64 *)ws_required,
                       (hipStream_t)stream, opts, false);
 }
 
@@ -796,7 +813,7 @@ int orbit_workspace_query_batched(const uint64_t *vptr, uint32_t num_graphs,
     if (hipMalloc(&tmp, L.p1_end) != hipSuccess) return ORB_E_DEVICE;
     u64 req = 0;
     int rc = count_impl(row_ptr, col_idx, n, m, (const u64 *)vptr, num_graphs, k_max, nullptr,
-                        tmp, L.p1_end, &req, (hipStream_t)stream, opts, true);
+                        nullptr, tmp, L.p1_end, &req, (hipStream_t)stream, opts, true);
     (void)hipFree(tmp);
     if (rc) return rc;
     *bytes = req;
@@ -817,7 +834,7 @@ int orbit_autotune(const uint64_t *vptr, uint32_t num_graphs, const uint32_t *ro
     hipStream_t s = (hipStream_t)stream;
     auto run = [&](const orb_opts &x, float *ms) -> int {
         int rc = count_impl(row_ptr, col_idx, n, m, (const u64 *)vptr, num_graphs, k_max,
-                            (u64 *)counts, workspace, ws_bytes, nullptr, s, &x, false);
+                            (u64 *)counts, nullptr, workspace, ws_bytes, nullptr, s, &x, false);
         if (rc) return rc;
         float t = 0;
         for (int i = 0; i < g_nphase; i++) t += g_phase_ms[i];
@@ -876,7 +893,7 @@ int orbit_plan_create(const uint64_t *vptr, uint32_t num_graphs, const uint32_t 
     // 1. an ordinary run validates the input and fixes the sizes
     Plan pl;
     int rc = count_impl(row_ptr, col_idx, n, m, (const u64 *)vptr, num_graphs, k_max,
-                        (u64 *)counts, workspace, ws_bytes, nullptr, s, &o, false, &pl);
+                        (u64 *)counts, nullptr, workspace, ws_bytes, nullptr, s, &o, false, &pl);
     if (rc) return rc;
     if (n == 0) return ORB_E_INVALID_ARG;  // nothing to capture
     // 2. the same launches, captured on a private stream
@@ -888,7 +905,7 @@ int orbit_plan_create(const uint64_t *vptr, uint32_t num_graphs, const uint32_t 
     }
     pl.capture = true;
     rc = count_impl(row_ptr, col_idx, n, m, (const u64 *)vptr, num_graphs, k_max,
-                    (u64 *)counts, workspace, ws_bytes, nullptr, cs, &o, false, &pl);
+                    (u64 *)counts, nullptr, workspace, ws_bytes, nullptr, cs, &o, false, &pl);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(cs, &g);
     (void)hipStreamDestroy(cs);

@@ -304,6 +304,18 @@ __global__ void k_zero_rows(unsigned char *base, u64 pitch, u64 width, u64 rows)
 __global__ void k_save_ntri(DevState *st) {
     if (GTID == 0) st->ntri = st->scan_total;
 }
+// Checks made during a replay, right after the step that fixes each size,
+// so that no later kernel runs on sizes its buffers were not made for:
+// what = 0: the largest graph of a batch is no larger than planned;
+// what = 1: peeling finished within the planned launches;
+// what = 2: the triangle count equals the planned one.
+__global__ void k_plan_guard(DevState *st, int what, u64 expect) {
+    if (GTID != 0) return;
+    const bool bad = what == 0 ? st->gmax > expect
+                   : what == 1 ? st->alive != 0
+                               : st->scan_total != expect;
+    if (bad) atomicOr(&st->err, ERRB_INTERNAL);
+}
 __global__ void k_plan_check(DevState *st, u64 ntri, u32 maxlevel, u32 gmax) {
     if (GTID == 0 && (st->alive != 0 || st->ntri != ntri || st->maxlevel != maxlevel ||
                       st->gmax != gmax))

@@ -6,12 +6,13 @@ loads the library and fails loudly if it has not been built.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import os
 
 import numpy as np
 
-from .build import LIB
+from .build import LIB, LIB_TILES
 
 NORB = 73
 ORB_NONINDUCED = 0x1
@@ -42,10 +43,10 @@ class _Opts(ctypes.Structure):
                 ("steps_out", ctypes.c_void_p), ("pass_cycles_out", ctypes.c_void_p)]
 
 
-def _load():
-    if not os.path.exists(LIB):
-        raise ImportError(f"{LIB} is not built; run paper_1911_10616_amd.build.build()")
-    lib = ctypes.CDLL(LIB)
+def _load(path=LIB):
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run paper_1911_10616_amd.build.build()")
+    lib = ctypes.CDLL(path)
     vp = ctypes.c_void_p
     u64 = ctypes.c_uint64
     lib.orbit_num_orbits.argtypes = [ctypes.c_int]
@@ -55,7 +56,7 @@ def _load():
     lib.orbit_workspace_query.argtypes = [vp, vp, ctypes.c_uint32, u64, ctypes.c_int, vp,
                                           ctypes.POINTER(_Opts), ctypes.POINTER(u64)]
     lib.orbit_workspace_query.restype = ctypes.c_int
-    lib.orbit_count_ex.argtypes = [vp, vp, ctypes.c_uint32, u64, ctypes.c_int, vp, vp, u64,
+    lib.orbit_count_ex.argtypes = [vp, vp, ctypes.c_uint32, u64, ctypes.c_int, vp, vp, vp, u64,
                                    ctypes.POINTER(u64), vp, ctypes.POINTER(_Opts)]
     lib.orbit_count_ex.restype = ctypes.c_int
     lib.orbit_strerror.argtypes = [ctypes.c_int]
@@ -97,6 +98,22 @@ def _load():
 
 
 _lib = _load()
+_loaded = {LIB: _lib}
+
+
+@contextlib.contextmanager
+def using_library(path=LIB_TILES):
+    """Route every call of this module to another build of the library
+    (the tests use the small-tile build) inside the with-block."""
+    global _lib
+    if path not in _loaded:
+        _loaded[path] = _load(path)
+    old = _lib
+    _lib = _loaded[path]
+    try:
+        yield
+    finally:
+        _lib = old
 
 
 def num_orbits(k_max: int) -> int:
@@ -189,12 +206,15 @@ class Counter:
         self.ws = torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8, device=self.rp.device)
         self.out = torch.empty((max(self.n, 1), self.K), dtype=torch.int64, device=self.rp.device)
 
-    def run(self, timing=False):
+    def run(self, timing=False, overflow_flags=None):
+        """Counts into self.out; overflow_flags: optional uint8 device tensor
+        of n entries that receives the overflow flags (1 = the row may have
+        wrapped modulo 2^64)."""
         need = ctypes.c_uint64(0)
         o = self.topts if timing else self.opts
         st = _lib.orbit_count_ex(ctypes.c_void_p(self.rp.data_ptr()),
                                  ctypes.c_void_p(self.ci.data_ptr()), self.n, self.m, self.k_max,
-                                 ctypes.c_void_p(self.out.data_ptr()),
+                                 ctypes.c_void_p(self.out.data_ptr()), _ptr(overflow_flags),
                                  ctypes.c_void_p(self.ws.data_ptr()), self.ws_bytes,
                                  ctypes.byref(need), _stream_ptr(self.stream), ctypes.byref(o))
         if st:
@@ -203,10 +223,22 @@ class Counter:
 
 
 def count(row_ptr, col_idx, k_max=5, noninduced=False, num_wg=0, groups="auto",
-          relabel=False) -> np.ndarray:
-    """uint64[n, K] orbit counts (induced unless noninduced=True)."""
+          relabel=False, overflow_flags=None):
+    """Orbit counts of one graph as a torch tensor [n, K] on the GPU: int64
+    holding the uint64 bits (induced unless noninduced=True).  overflow_flags:
+    optional uint8 device tensor [n] for the overflow flags."""
     c = Counter(row_ptr, col_idx, k_max, noninduced, num_wg, groups=groups, relabel=relabel)
-    return c.run().cpu().numpy().view(np.uint64)
+    return c.run(overflow_flags=overflow_flags).clone()
+
+
+def to_u64(t) -> np.ndarray:
+    """A count tensor as a host numpy uint64 array."""
+    return t.cpu().numpy().view(np.uint64)
+
+
+def count_np(row_ptr, col_idx, k_max=5, **kw) -> np.ndarray:
+    """count() copied to the host as uint64[n, K]."""
+    return to_u64(count(row_ptr, col_idx, k_max, **kw))
 
 
 def count_minimal(row_ptr, col_idx, k_max=5) -> np.ndarray:
@@ -408,11 +440,13 @@ def mlp_train(weights, features, steps, iters=300, batch=4096, lr=3e-3, seed=7, 
     return float(state[-1].item())
 
 
-def raw_count_ex(rp, ci, n, m, k_max, counts, ws, ws_bytes, flags=0, stream=None):
+def raw_count_ex(rp, ci, n, m, k_max, counts, ws, ws_bytes, flags=0, stream=None,
+                 overflow_flags=None):
     """Direct call of orbit_count_ex with explicit arguments (tests)."""
     need = ctypes.c_uint64(0)
     o = _Opts(flags, 0, 0, 0, None, None, None)
     st = _lib.orbit_count_ex(ctypes.c_void_p(rp), ctypes.c_void_p(ci), n, m, k_max,
-                             ctypes.c_void_p(counts), ctypes.c_void_p(ws), ws_bytes,
+                             ctypes.c_void_p(counts), ctypes.c_void_p(overflow_flags),
+                             ctypes.c_void_p(ws), ws_bytes,
                              ctypes.byref(need), _stream_ptr(stream), ctypes.byref(o))
     return st, int(need.value)

@@ -68,7 +68,7 @@ def test_batch_equals_union_and_oracle_sample(orbit):
     vptr, rp, ci = gg.batch_small(1000, 104)
     _say("batch of 1000, n", len(rp) - 1, "m", ci.size // 2)
     got = orbit.count_batched(vptr, rp, ci, 5)
-    union = orbit.count(rp, ci, 5)
+    union = orbit.count_np(rp, ci, 5)
     np.testing.assert_array_equal(got, union)
     for g in (0, 1, 2, 3, 998, 999):
         a, b = int(vptr[g]), int(vptr[g + 1])

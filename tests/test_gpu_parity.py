@@ -42,7 +42,7 @@ def test_random_graphs_induced(orbit, name, make):
     rp, ci = make()
     _say("case", name, len(rp) - 1, ci.size // 2)
     ref = oracle.induced_counts(rp, ci, threads=8)
-    got = orbit.count(rp, ci, 5)
+    got = orbit.count_np(rp, ci, 5)
     np.testing.assert_array_equal(got, ref)
 
 
@@ -50,7 +50,7 @@ def test_random_graphs_induced(orbit, name, make):
 def test_random_graphs_noninduced(orbit, seed):
     rp, ci = gg.erdos_renyi(10 + seed, [0.3, 0.5, 0.7, 0.9][seed % 4], 7000 + seed)
     _say("noninduced seed", seed)
-    np.testing.assert_array_equal(orbit.count(rp, ci, 5, noninduced=True),
+    np.testing.assert_array_equal(orbit.count_np(rp, ci, 5, noninduced=True),
                                   oracle.noninduced_counts(rp, ci))
 
 
@@ -61,9 +61,9 @@ def test_smaller_kmax(orbit, k_max):
         rp, ci = gg.erdos_renyi(30, 0.25, 8000 + s)
         _say("kmax", k_max, "seed", s)
         ref = oracle.induced_counts(rp, ci, kmax=k_max)[:, :K]
-        np.testing.assert_array_equal(orbit.count(rp, ci, k_max), ref)
+        np.testing.assert_array_equal(orbit.count_np(rp, ci, k_max), ref)
         refn = oracle.noninduced_counts(rp, ci, kmax=k_max)[:, :K]
-        np.testing.assert_array_equal(orbit.count(rp, ci, k_max, noninduced=True), refn)
+        np.testing.assert_array_equal(orbit.count_np(rp, ci, k_max, noninduced=True), refn)
 
 
 def _special():
@@ -86,7 +86,7 @@ def _special():
 def test_special_graphs(orbit, name, make):
     rp, ci = make()
     _say("special", name)
-    np.testing.assert_array_equal(orbit.count(rp, ci, 5), oracle.induced_counts(rp, ci))
+    np.testing.assert_array_equal(orbit.count_np(rp, ci, 5), oracle.induced_counts(rp, ci))
 
 
 def test_hub_larger_than_lds_tile(orbit):
@@ -94,7 +94,7 @@ def test_hub_larger_than_lds_tile(orbit):
     # tile (384), exercising the global-memory bit rows
     rp, ci = gg.complete(420)
     _say("K420")
-    got = orbit.count(rp, ci, 5)
+    got = orbit.count_np(rp, ci, 5)
     from math import comb
     assert (got[:, 0] == 419).all() and (got[:, 3] == comb(419, 2)).all()
     assert (got[:, 14] == comb(419, 3)).all() and (got[:, 72] == comb(419, 4)).all()
@@ -144,10 +144,10 @@ def test_book_long_triangle_lists(orbit, k):
     _say("book", k)
     rp, ci = _book(k)
     exp = _book_counts(k)
-    np.testing.assert_array_equal(orbit.count(rp, ci, 5), exp)
+    np.testing.assert_array_equal(orbit.count_np(rp, ci, 5), exp)
     rp2, ci2 = gg.relabel(rp, ci, 77)
     perm = np.random.Generator(np.random.PCG64(77)).permutation(k + 2)
-    np.testing.assert_array_equal(orbit.count(rp2, ci2, 5)[perm], exp)
+    np.testing.assert_array_equal(orbit.count_np(rp2, ci2, 5)[perm], exp)
 
 
 def test_er2000_full(orbit):
@@ -155,7 +155,7 @@ def test_er2000_full(orbit):
     rp, ci = gg.workload("er2000")
     _say("er2000")
     ref = oracle.induced_counts(rp, ci, threads=16)
-    np.testing.assert_array_equal(orbit.count(rp, ci, 5), ref)
+    np.testing.assert_array_equal(orbit.count_np(rp, ci, 5), ref)
 
 
 def test_entry_points_agree_and_deterministic(orbit):
@@ -168,7 +168,7 @@ def test_entry_points_agree_and_deterministic(orbit):
     np.testing.assert_array_equal(a, b1)
     np.testing.assert_array_equal(b1, b2)
     # a different number of persistent workgroups changes only the schedule
-    b3 = orbit.count(rp, ci, 5, num_wg=7)
+    b3 = orbit.count_np(rp, ci, 5, num_wg=7)
     np.testing.assert_array_equal(b1, b3)
 
 
@@ -231,9 +231,9 @@ def test_execution_groups(orbit, groups):
               gg.chung_lu(500, 8.0, 2.1, 80.0, 2000, 13), gg.complete(12), _book(70)]
     for i, (rp, ci) in enumerate(graphs):
         _say("groups", groups, "graph", i)
-        np.testing.assert_array_equal(orbit.count(rp, ci, 5, groups=groups),
+        np.testing.assert_array_equal(orbit.count_np(rp, ci, 5, groups=groups),
                                       oracle.induced_counts(rp, ci, threads=8))
-        np.testing.assert_array_equal(orbit.count(rp, ci, 5, noninduced=True, groups=groups),
+        np.testing.assert_array_equal(orbit.count_np(rp, ci, 5, noninduced=True, groups=groups),
                                       oracle.noninduced_counts(rp, ci, threads=8))
 
 
@@ -245,18 +245,18 @@ def test_relabelled_counting(orbit):
               gg.barabasi_albert(200, 3, 72), gg.erdos_renyi(40, 0.4, 73), gg.complete(12)]
     for i, (rp, ci) in enumerate(graphs):
         _say("relabel graph", i)
-        np.testing.assert_array_equal(orbit.count(rp, ci, 5, relabel=True),
+        np.testing.assert_array_equal(orbit.count_np(rp, ci, 5, relabel=True),
                                       oracle.induced_counts(rp, ci, threads=8))
-        np.testing.assert_array_equal(orbit.count(rp, ci, 5, noninduced=True, relabel=True),
+        np.testing.assert_array_equal(orbit.count_np(rp, ci, 5, noninduced=True, relabel=True),
                                       oracle.noninduced_counts(rp, ci, threads=8))
     for k in (300, 5000):
         _say("relabel book", k)
         rp, ci = gg.relabel(*_book(k), 5)
         perm = np.random.Generator(np.random.PCG64(5)).permutation(k + 2)
-        got = orbit.count(rp, ci, 5, relabel=True)
+        got = orbit.count_np(rp, ci, 5, relabel=True)
         np.testing.assert_array_equal(got[perm], _book_counts(k))
     rp, ci = gg.erdos_renyi(30, 0.3, 74)
-    np.testing.assert_array_equal(orbit.count(rp, ci, 4, relabel=True),
+    np.testing.assert_array_equal(orbit.count_np(rp, ci, 4, relabel=True),
                                   oracle.induced_counts(rp, ci, kmax=4)[:, :15])
 
 

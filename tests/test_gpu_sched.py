@@ -156,7 +156,7 @@ def test_schedule_argument_errors(orbit):
         o = orbit._Opts(0, 0, sched, groups, wp, None, None)
         need = ctypes.c_uint64(0)
         st = lib.orbit_count_ex(ctypes.c_void_p(rpd.data_ptr()), ctypes.c_void_p(cid.data_ptr()),
-                                5, 10, 5, ctypes.c_void_p(out.data_ptr()),
+                                5, 10, 5, ctypes.c_void_p(out.data_ptr()), None,
                                 ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.byref(need),
                                 None, ctypes.byref(o))
         assert st == want, (sched, groups, st)

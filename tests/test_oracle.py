@@ -319,3 +319,76 @@ def test_relabel_permutes_counts():
     a = oracle.induced_counts(rp, ci)
     b = oracle.induced_counts(rp2, ci2)
     np.testing.assert_array_equal(b[perm], a)
+
+
+# ------------------------------------------------------------ overflow bound
+
+# every rooted tree shape with 3..5 vertices as an edge list on 0..k-1, root 0
+_SHAPES = {
+    "P3_end": [(0, 1), (1, 2)], "P3_mid": [(0, 1), (0, 2)],
+    "P4_end": [(0, 1), (1, 2), (2, 3)], "S3_leaf": [(0, 1), (1, 2), (1, 3)],
+    "P4_inner": [(0, 1), (1, 2), (0, 3)], "S3_centre": [(0, 1), (0, 2), (0, 3)],
+    "P5_end": [(0, 1), (1, 2), (2, 3), (3, 4)], "fork_tip": [(0, 1), (1, 2), (2, 3), (2, 4)],
+    "chair_end": [(0, 1), (1, 2), (2, 3), (1, 4)], "S4_leaf": [(0, 1), (1, 2), (1, 3), (1, 4)],
+    "P5_second": [(0, 1), (1, 2), (2, 3), (0, 4)], "fork_second": [(0, 1), (1, 2), (1, 3), (0, 4)],
+    "P5_centre": [(0, 1), (1, 2), (0, 3), (3, 4)], "chair_deg3": [(0, 1), (1, 2), (0, 3), (0, 4)],
+    "S4_centre": [(0, 1), (0, 2), (0, 3), (0, 4)],
+}
+
+
+def _brute_homs(adj, edges, k, u):
+    """Edge-preserving maps of the tree on 0..k-1 into the graph with 0 -> u."""
+    import itertools
+    n = len(adj)
+    tot = 0
+    for rest in itertools.product(range(n), repeat=k - 1):
+        f = (u,) + rest
+        if all(f[b] in adj[f[a]] for a, b in edges):
+            tot += 1
+    return tot
+
+
+def test_rooted_tree_shapes_are_all_trees():
+    """The shape table lists each rooted tree on 3..5 vertices once, with its
+    root-fixing automorphism count: there are 2, 4 and 9 rooted trees, and
+    labelling the k-1 other vertices of each shape in (k-1)!/|Aut| ways must
+    give every labelled tree exactly once -- k^(k-2) of them (Cayley)."""
+    from math import factorial
+    for k, shapes in oracle.ROOTED_TREES.items():
+        assert len(shapes) == {3: 2, 4: 4, 5: 9}[k]
+        labelled = sum(factorial(k - 1) // aut for _, aut in shapes)
+        assert labelled == k ** (k - 2)
+        for name, _ in shapes:
+            assert len(_SHAPES[name]) == k - 1
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_rooted_tree_homs_brute_force(seed):
+    rp, ci = gg.erdos_renyi(6, 0.5, 500 + seed)
+    adj = bf.adjacency_sets(rp, ci)
+    h = oracle.rooted_tree_homs(rp, ci)
+    for name, edges in _SHAPES.items():
+        k = 1 + len(edges)
+        for u in range(len(rp) - 1):
+            assert h[name][u] == _brute_homs(adj, edges, k, u), (name, u)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_count_bound_holds(seed):
+    """The bound exceeds every non-induced (hence induced) count of every
+    vertex, on dense and sparse random graphs and a star."""
+    graphs = [gg.erdos_renyi(9, [0.3, 0.6, 0.9][seed % 3], 600 + seed),
+              gg.barabasi_albert(12, 3, 610 + seed), gg.star(6)]
+    for rp, ci in graphs:
+        b = oracle.count_bound(rp, ci)
+        nic = oracle.noninduced_counts(rp, ci).astype(np.float64)
+        assert np.all(nic <= b[:, None])
+
+
+def test_overflow_flags_star():
+    """Star with 150,000 leaves: the centre's C(s,4) exceeds 2^64 and is
+    flagged; the leaves' counts stay below 10^15 and are not."""
+    rp, ci = gg.star(150_000)
+    f = oracle.overflow_flags(rp, ci)
+    assert f[0] == 1 and f[1:].sum() == 0
+    assert comb(150_000, 4) > 2 ** 64
