@@ -66,6 +66,8 @@ extern "C" {
 #define ORB_E_INTERNAL (-9)     /* internal consistency check failed */
 #define ORB_E_BATCH (-10)       /* batched input: graph offsets not 0..n and non-decreasing,
                                    or an edge joining two graphs */
+#define ORB_E_TOO_LARGE (-11)   /* orbit_count_noalloc: the count needs more memory than its
+                                   static buffer (orbit_noalloc_capacity()) holds */
 
 /* option flags */
 #define ORB_NONINDUCED 0x1u /* return non-induced counts DM(u, theta) */
@@ -124,6 +126,25 @@ int orbit_num_orbits(int k_max);
  * m = number of undirected edges (col_idx has 2m entries). */
 int orbit_count(const uint32_t *row_ptr, const uint32_t *col_idx, uint32_t n, uint64_t m,
                 int k_max, uint64_t *counts);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the count
+ * of orbit_count_ex with default options, whose workspace is a static
+ * device array of orbit_noalloc_capacity() bytes (64 MiB) that every GPU the
+ * library runs on holds until the process ends.  Calls no hipMalloc or
+ * hipFree and allocates through no library.  The caller passes the CSR and
+ * counts (device pointers, as for orbit_count_ex); `stream` may be NULL.
+ * Returns ORB_E_TOO_LARGE, before any kernel runs when n and m alone are
+ * too large, else after the graph was validated and its triangles counted,
+ * when the count does not fit (fewer persistent workgroups are used first).
+ * All calls on one GPU share that GPU's array: calls that overlap on one
+ * GPU (other threads, other streams) race and must be serialised by the
+ * caller.  Like orbit_count_ex it returns after the stream has finished. */
+int orbit_count_noalloc(const uint32_t *row_ptr, const uint32_t *col_idx, uint32_t n,
+                        uint64_t m, int k_max, uint64_t *counts, void *stream);
+
+/* Size in bytes of orbit_count_noalloc's static buffer (host only). */
+uint64_t orbit_noalloc_capacity(void);
 
 /* Workspace size that orbit_count_ex needs for this graph.  The size
  * depends on the number of triangles, so this call validates the graph,

@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 
 #include "orbit_common.h"
@@ -492,7 +493,7 @@ int relabel_input(const u32 *rp, const u32 *ci, u32 n, u64 m, void *ws, const La
 int count_impl(const u32 *rp, const u32 *ci, u32 n, u64 m, const u64 *vptr, u32 B, int k_max,
                u64 *counts, unsigned char *ovf, void *ws,
                u64 ws_bytes, u64 *ws_required, hipStream_t s, const orb_opts *opts,
-               bool query_only, Plan *pl = nullptr) {
+               bool query_only, Plan *pl = nullptr, u32 *nwg_fit = nullptr) {
     const bool cap = pl && pl->capture;
     const u32 flags = opts ? opts->flags : 0u;
     const int K = orbit_num_orbits(k_max);
@@ -540,6 +541,15 @@ int count_impl(const u32 *rp, const u32 *ci, u32 n, u64 m, const u64 *vptr, u32 
         (greq == ORB_GROUPS_AUTO && mapn <= kWaveGroupMaxMap && dmax <= kWaveGroupMaxOut);
     layout_phase2(L, n, mapn, m, ntri, dmax, k_max, ni_in_out, opts ? opts->num_wg : 0,
                   wave_groups ? WAVES_PER_WG : 1);
+    if (nwg_fit) {  // fewer persistent workgroups until the workspace fits ws_bytes
+        u32 w = L.nwg;
+        while (L.total > ws_bytes && w > 1) {
+            w /= 2;
+            layout_phase2(L, n, mapn, m, ntri, dmax, k_max, ni_in_out, w,
+                          wave_groups ? WAVES_PER_WG : 1);
+        }
+        *nwg_fit = L.nwg;
+    }
     if (ws_required) *ws_required = L.total;
     if (query_only) return ORB_OK;
     if (L.total > ws_bytes) return ORB_E_WORKSPACE;
@@ -739,6 +749,34 @@ int count_impl(const u32 *rp, const u32 *ci, u32 n, u64 m, const u64 *vptr, u32 
     return ORB_OK;
 }
 
+// ---- the entry point that allocates nothing: its workspace is a static
+// device array.  Each GPU the library runs on holds its own copy for the
+// life of the process.  In host code the array's name stands for a host-side
+// stand-in, so the device address of the current GPU's copy is looked up
+// once per device (hipGetSymbolAddress, with that device current) and only
+// that address is ever handed to kernels.
+#ifndef ORB_NOALLOC_BYTES
+#define ORB_NOALLOC_BYTES (64ull << 20)
+#endif
+static __device__ __align__(256) unsigned char scratch[ORB_NOALLOC_BYTES];
+const int kMaxDevices = 64;
+void *g_scratch_ptr[kMaxDevices];
+std::mutex g_scratch_mu;
+
+int scratch_of_current_device(void **out) {
+    int dev = -1;
+    HCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return ORB_E_DEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return ORB_E_DEVICE;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return ORB_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -759,6 +797,32 @@ int orbit_count_ex(const uint32_t *row_ptr, const uint32_t *col_idx, uint32_t n,
     return count_impl(row_ptr, col_idx, n, m, nullptr, 0, k_max, (u64 *)counts, overflow_flags,
                       workspace, ws_bytes, (u64 *)ws_required, (hipStream_t)stream, opts, false);
 }
+
+int orbit_count_noalloc(const uint32_t *row_ptr, const uint32_t *col_idx, uint32_t n,
+                        uint64_t m, int k_max, uint64_t *counts, void *stream) {
+    if (!orbit_num_orbits(k_max) || 2 * m >= (1ull << 32)) return ORB_E_INVALID_ARG;
+    Layout L;
+    layout_phase1(L, n, m);
+    if (L.p1_end > ORB_NOALLOC_BYTES) return ORB_E_TOO_LARGE;
+    void *ws = nullptr;
+    int rc = scratch_of_current_device(&ws);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    // size the count for the static buffer (validates the graph on the way)
+    u32 nwg = 0;
+    u64 need = 0;
+    rc = count_impl(row_ptr, col_idx, n, m, nullptr, 0, k_max, (u64 *)counts, nullptr, ws,
+                    ORB_NOALLOC_BYTES, &need, s, nullptr, true, nullptr, &nwg);
+    if (rc) return rc;
+    if (need > ORB_NOALLOC_BYTES) return ORB_E_TOO_LARGE;
+    orb_opts o;
+    memset(&o, 0, sizeof o);
+    o.num_wg = nwg;
+    return count_impl(row_ptr, col_idx, n, m, nullptr, 0, k_max, (u64 *)counts, nullptr, ws,
+                      ORB_NOALLOC_BYTES, nullptr, s, &o, false);
+}
+
+uint64_t orbit_noalloc_capacity(void) { return ORB_NOALLOC_BYTES; }
 
 int orbit_workspace_query(const uint32_t *row_ptr, const uint32_t *col_idx, uint32_t n,
                           uint64_t m, int k_max, void *stream, const orb_opts *opts,
@@ -1013,6 +1077,8 @@ const char *orbit_strerror(int status) {
         case ORB_E_DEVICE: return "HIP call failed";
         case ORB_E_INTERNAL: return "internal consistency check failed";
         case ORB_E_BATCH: return "batched input: bad graph offsets or an edge joining two graphs";
+        case ORB_E_TOO_LARGE:
+            return "graph needs more device memory than orbit_count_noalloc's static buffer holds";
         default: return "unknown status";
     }
 }

@@ -27,7 +27,8 @@ EXPORTS = ("orbit_num_orbits", "orbit_count", "orbit_workspace_query", "orbit_co
            "orbit_strerror", "orbit_last_phase_times", "orbit_last_stats", "orbit_mlp_init",
            "orbit_mlp_predict", "orbit_mlp_grad", "orbit_mlp_train", "orbit_count_batched",
            "orbit_workspace_query_batched", "orbit_autotune", "orbit_plan_create",
-           "orbit_plan_launch", "orbit_plan_status", "orbit_plan_destroy")
+           "orbit_plan_launch", "orbit_plan_status", "orbit_plan_destroy",
+           "orbit_count_noalloc", "orbit_noalloc_capacity")
 
 
 class OrbError(RuntimeError):
@@ -94,6 +95,10 @@ def _load(path=LIB):
         f.restype = ctypes.c_int
     lib.orbit_plan_destroy.argtypes = [vp]
     lib.orbit_plan_destroy.restype = ctypes.c_int
+    lib.orbit_count_noalloc.argtypes = [vp, vp, u32, u64, ctypes.c_int, vp, vp]
+    lib.orbit_count_noalloc.restype = ctypes.c_int
+    lib.orbit_noalloc_capacity.argtypes = []
+    lib.orbit_noalloc_capacity.restype = u64
     return lib
 
 
@@ -255,6 +260,20 @@ def count_minimal(row_ptr, col_idx, k_max=5) -> np.ndarray:
     if st:
         raise OrbError(st, "orbit_count")
     return out[:n].cpu().numpy().view(np.uint64)
+
+
+def count_noalloc(row_ptr, col_idx, k_max=5, stream=None):
+    """orbit_count_noalloc: the count in the library's static buffer (no
+    device allocation inside the call); torch tensor as count()."""
+    import torch
+    rp, ci = _dev_csr(row_ptr, col_idx)
+    n = rp.numel() - 1
+    m = int(rp[-1].item()) // 2
+    out = torch.empty((max(n, 1), num_orbits(k_max)), dtype=torch.int64, device=rp.device)
+    _check(_lib.orbit_count_noalloc(ctypes.c_void_p(rp.data_ptr()), ctypes.c_void_p(ci.data_ptr()),
+                                    n, m, k_max, ctypes.c_void_p(out.data_ptr()),
+                                    _stream_ptr(stream)), "orbit_count_noalloc")
+    return out[:n]
 
 
 def last_phase_times():

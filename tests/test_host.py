@@ -12,7 +12,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def _declared_functions():
     txt = open(os.path.join(ROOT, "include", "orbit_hip.h")).read()
-    return sorted(set(re.findall(r"^\s*(?:int|const char \*)\s*(orbit_\w+)\s*\(", txt, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:int|uint64_t|const char \*)\s*(orbit_\w+)\s*\(", txt, re.M)))
 
 
 def test_library_exports_every_declared_symbol():
