@@ -21,8 +21,7 @@ SOURCES = ["orbit_lib.hip", "orbit_prep.hip", "orbit_count.hip", "orbit_combine.
            "orbit_sched.hip", "orbit_common.h", "orbit_tables.h"]
 # tile sizes of the test build (each the smallest its kernel accepts or a
 # size a 40..120-vertex graph exceeds)
-SMALL_TILES = {"CLQ_LDS_D": 16, "PAIR_KMAP_LDS": 32, "C5_HSET": 64, "TL_SORT_LDS": 128,
-               "PAIR_HUB_LDS": 64}
+SMALL_TILES = {"CLQ_LDS_D": 16, "PAIR_KMAP_LDS": 16, "C5_HSET": 64, "TL_SORT_LDS": 128}
 
 
 def hipcc_command(out: str = LIB, defines=None):

@@ -683,6 +683,13 @@ __global__ void k_tri_k4terms(const u32 *src, const u32 *ci, const u32 *T, u64 n
     }
 }
 
+// lanes of one wave see each other's LDS and memory writes after this
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
 // ---- pair sweep over wedges and diamonds (the undirected 2-hop sweep).
 // For a source a and every b > a with s = |N(a) & N(b)| >= 2 (pairs with
 // s <= 1 contribute to none of these orbits), with S = N(a) & N(b):
@@ -698,7 +705,9 @@ __global__ void k_tri_k4terms(const u32 *src, const u32 *ci, const u32 *T, u64 n
 //     68: C(K,2) to a and to b;  Q(a,y) = sum_b C(K,2) (orbit 69 of y is half
 //     the sum of Q over the arcs into y).
 // The remaining subtractions (36: -N13, 51: -2 N12, 62: -N13) happen in the
-// per-vertex combine.
+// per-vertex combine.  a's share tb (s-1) of orbit 51 is summed wedge by
+// wedge in the centre pass, T(y,b) (s-1) per wedge a - y - b, once s is
+// final, so the wedge pass needs a single atomic per wedge.
 // Profiling of the pair sweep: pass_cycles[k-1] accumulates the shader
 // clock cycles that execution groups spend in pass k (1 wedges, 2 wheel
 // maps, 3 pair terms, 4 centre terms); the group synchronises at each
@@ -714,7 +723,9 @@ __device__ inline void pass_mark_g(u64 *pc, int k, u64 &t) {
 }
 #define pass_mark(pc, k, t) pass_mark_g<GP>(pc, k, t)
 
-// wheel maps of up to this many positions live in LDS (per wave)
+// wheel maps of up to this many positions live in LDS (per wave); in
+// workgroup execution groups the four waves' maps together hold one map of
+// 6 x PAIR_KMAP_LDS positions for the arcs to larger neighbourhoods
 #ifndef PAIR_KMAP_LDS
 #define PAIR_KMAP_LDS 2048
 #endif
@@ -731,29 +742,45 @@ __device__ inline void pass_mark_g(u64 *pc, int k, u64 &t) {
 #define VA_62 7
 #define VACC(u, k) vacc[(u64)(u) * 8 + (k)]
 
-// Per-vertex record of the pair (a, b): everything the passes touch for b
-// lies in one 32-byte sector, so a wedge's three updates, the centre pass's
-// two reads and the pair terms' five reads cost one sector each.
-struct PairRec {
-    u32 s;    // |N(a) & N(b)|
-    u32 adj;  // b ~ a
-    u64 ta;   // sum over y in S of T(a,y)
-    u64 tb;   // sum over y in S of T(y,b)
-    u64 e2;   // 2 |E(S)|
-};
-struct PairScratch {
-    PairRec *R;       // n records
+// Per-pair state of the source a, one array per field, indexed by b
+// (within b's graph):
+//   sta[b]: bit 63 = [a ~ b].  While d(a) < 2^20, bits 40..62 hold s and
+//           bits 0..39 hold ta (s <= d(a) < 2^20 and ta < d(a)^2 < 2^40), so
+//           a wedge costs one atomic; for a source of higher degree bits
+//           0..62 hold s and ext[b] holds ta.
+//   e2[b]:  2 |E(S)|, summed from the wheel maps.
+#define PS_ADJ (1ull << 63)
+#define PS_SHIFT 40
+#define PS_TA_MASK ((1ull << PS_SHIFT) - 1)
+#define PS_WIDE_DEG (1u << 20)
+struct PairState {
+    u64 *sta, *e2, *ext;
     u32 *touched;
-    u32 *K;   // WAVES_PER_WG x n
-    u32 *tk;  // WAVES_PER_WG x n
+    u32 *K, *tk;  // wave groups only: per-wave global wheel maps, WAVES_PER_WG x n each
 };
-__device__ inline PairScratch pair_scratch(unsigned char *base, u32 n) {
-    PairScratch p;
-    p.R = (PairRec *)base;
-    p.touched = (u32 *)align256((unsigned char *)(p.R + n));
-    p.K = (u32 *)align256((unsigned char *)(p.touched + n));
-    p.tk = (u32 *)align256((unsigned char *)(p.K + (u64)WAVES_PER_WG * n));
+__device__ inline PairState pair_state(unsigned char *base, u32 n, bool wave_maps) {
+    PairState p;
+    p.sta = (u64 *)base;
+    p.e2 = (u64 *)align256((unsigned char *)(p.sta + n));
+    p.ext = (u64 *)align256((unsigned char *)(p.e2 + n));
+    p.touched = (u32 *)align256((unsigned char *)(p.ext + n));
+    p.K = wave_maps ? (u32 *)align256((unsigned char *)(p.touched + n)) : nullptr;
+    p.tk = wave_maps ? (u32 *)align256((unsigned char *)(p.K + (u64)WAVES_PER_WG * n)) : nullptr;
     return p;
+}
+__device__ inline u64 ps_s(u64 v, bool wide) {
+    return wide ? (v & ~PS_ADJ) : ((v & ~PS_ADJ) >> PS_SHIFT);
+}
+
+// Drain of one wheel-map entry: K = K(a,y,b) for the b at position pos of
+// N(y) (slot by + pos).  Returns C(K,2) and adds K (s(a,b) - 2) to c64.
+__device__ inline u64 wheel_drain(u32 kab, u32 b, u32 vb, const PairState &P, bool wide,
+                                  u64 *vacc, u64 &c64) {
+    const u64 v = c2((i64)kab);
+    atomic_add_u64(&VACC(b, VA_68), v);
+    atomicAdd(&P.e2[b - vb], (u64)kab);
+    c64 += (u64)kab * (ps_s(P.sta[b - vb], wide) - 2);
+    return v;
 }
 
 template <class GP>
@@ -764,6 +791,7 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
                                              const u32 *order, u32 mapn, const u32 *gbase,
                                              u32 kl, u64 *steps, u64 *pass_cycles, u64 *Q,
                                              u64 *vacc, const DevState *st) {
+    constexpr bool kWaveGroups = GP::per_wg > 1;
     __shared__ u32 sh_q_[GP::per_wg][3], sh_nt_[GP::per_wg], sh_next_[GP::per_wg];
     u32 *sh_q = sh_q_[GP::id()];
     if (GP::rank() == 0) { sh_q[0] = 0; sh_q[1] = 0; }
@@ -771,17 +799,22 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
     u32 &sh_next = sh_next_[GP::id()];
     __shared__ u32 sh_ntk[WAVES_PER_WG];
     __shared__ u64 sh_red[WAVES_PER_WG];
+    __shared__ u32 sh_hub[WG], sh_nhub;  // workgroup groups: this chunk's arcs to hubs
     // dynamic LDS: per-wave wheel maps of kl positions (u32) and touched
-    // lists (u16), kl <= PAIR_KMAP_LDS
+    // lists (u16), kl <= PAIR_KMAP_LDS; in workgroup groups the same bytes
+    // also serve as one map of hmax = 6 kl positions for the hub arcs
     extern __shared__ u64 dyn_lds[];
     u32 *l_k0 = (u32 *)dyn_lds;
     unsigned short *l_tk0 = (unsigned short *)(l_k0 + WAVES_PER_WG * kl);
-    PairScratch P = pair_scratch(scratch + GP::global_id() * stride, mapn);
-    u32 *Kw = P.K + (u64)wave_in_wg() * mapn;
-    u32 *tkw = P.tk + (u64)wave_in_wg() * mapn;
+    u32 *hmap = l_k0;
+    const u32 hmax = 6 * kl;
+    PairState P = pair_state(scratch + GP::global_id() * stride, mapn, kWaveGroups);
+    u32 *Kw = kWaveGroups ? P.K + (u64)wave_in_wg() * mapn : nullptr;
+    u32 *tkw = kWaveGroups ? P.tk + (u64)wave_in_wg() * mapn : nullptr;
     // every thread of the workgroup clears its share, then all wait (the
     // slices belong to different waves)
-    for (u32 i = threadIdx.x; i < WAVES_PER_WG * kl; i += WG) l_k0[i] = 0;
+    for (u32 i = threadIdx.x; i < hmax; i += WG) hmap[i] = 0;
+    if (threadIdx.x == 0) sh_nhub = 0;
     __syncthreads();
     for (;;) {
         const u32 a = next_source<GP>(work, sh_q, order, n, st);
@@ -790,13 +823,14 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
         const u32 ba = rp[a], da = rp[a + 1] - ba;
         if (da < 2) continue;
         const u64 dega = da;
+        const bool wide = da >= PS_WIDE_DEG;
         u64 nsteps = 0;  // loop iterations of this thread for this source
         u64 t_pass = 0;  // clock at the last pass boundary (profiling)
-        for (u32 i = GP::rank(); i < da; i += GP::size) P.R[ci[ba + i] - vb].adj = 1;
+        for (u32 i = GP::rank(); i < da; i += GP::size) P.sta[ci[ba + i] - vb] = PS_ADJ;
         if (GP::rank() == 0) { sh_nt = 0; sh_next = 0; }
         GP::sync();
         if (pass_cycles) pass_mark(pass_cycles, 0, t_pass);
-        // wedges a - y - b, b > a
+        // wedges a - y - b, b > a: s and ta of the pair (a, b)
         wave_loop(&sh_next, da, [&](u32 iy) {
             const u32 say = ba + iy, y = ci[say];
             const u64 tay = T[say];
@@ -805,11 +839,15 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
             for (u32 s = st0 + lane_id(); s < ey; s += WAVE) {
                 const u32 b = ci[s];
                 nsteps++;
-                PairRec &r = P.R[b - vb];
-                u32 old = atomicAdd(&r.s, 1u);
+                u64 old;
+                if (!wide) {
+                    old = atomicAdd(&P.sta[b - vb], (1ull << PS_SHIFT) | tay) & ~PS_ADJ;
+                    old >>= PS_SHIFT;
+                } else {
+                    old = atomicAdd(&P.sta[b - vb], 1ull) & ~PS_ADJ;
+                    atomicAdd(&P.ext[b - vb], tay);
+                }
                 if (old == 0) P.touched[atomicAdd(&sh_nt, 1u)] = b;
-                atomicAdd(&r.ta, tay);
-                atomicAdd(&r.tb, (u64)T[s]);
             }
         });
         GP::sync();
@@ -824,16 +862,18 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
         // doubled inner edge count E2(a,b) = sum_y K(a,y,b) = 2 |E(S)|, and
         // the chord terms of orbit 64: y gets K(a,y,b) (s(a,b) - 2), i.e.
         // s - 2 per diamond with chord (y,z) -- z gets its share when it is
-        // the arc's end.
+        // the arc's end.  The map of (a, y) is indexed by b's position in
+        // N(y): a wave's LDS map when d(y) <= kl; else, in workgroup groups,
+        // the whole group's LDS map in windows of hmax positions (below), and
+        // in wave groups the wave's global map.
         if (lane_id() == 0) sh_ntk[wave_in_wg()] = 0;
         u64 l68 = 0;
         wave_loop(&sh_next, da, [&](u32 iy) {
             const u32 say = ba + iy, y = ci[say];
             if (T[say] == 0) return;
-            // the map of (a, y) is indexed by b's position in N(y): in LDS
-            // when d(y) fits, else in the wave's global map
             const u32 by = rp[y], dy = rp[y + 1] - by;
             const bool inl = dy <= kl;
+            if (!inl && !kWaveGroups) return;  // a hub arc: the whole group, below
             u32 *kc = inl ? l_k0 + wave_in_wg() * kl : Kw;
             unsigned short *tl_l = l_tk0 + wave_in_wg() * kl;
             TLView tv = tl_view(say, src, ci, rev, T, tl_ptr, tl);
@@ -875,21 +915,13 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
                     }
                 }
             }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            wave_sync();
             const u32 m = *ntk;
             u64 q = 0, c64 = 0;
             for (u32 t = lane_id(); t < m; t += WAVE) {
                 const u32 pos = inl ? (u32)tl_l[t] : tkw[t];
                 const u32 kab = atomicExch(&kc[pos], 0u);
-                const u32 b = ci[by + pos];
-                const u64 v = c2((i64)kab);
-                q += v;
-                atomic_add_u64(&VACC(b, VA_68), v);
-                PairRec &r = P.R[b - vb];
-                atomicAdd(&r.e2, (u64)kab);
-                c64 += (u64)kab * ((u64)r.s - 2);
+                q += wheel_drain(kab, ci[by + pos], vb, P, wide, vacc, c64);
             }
             q = wave_sum_u64(q);
             c64 = wave_sum_u64(c64);
@@ -899,48 +931,134 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
                 *ntk = 0;
             }
             l68 += q;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            wave_sync();
         });
         GP::sync();
-        // l68 is uniform within each wave (computed from wave sums)
+        if (!kWaveGroups) {
+            // arcs to hubs (d(y) > kl), one at a time by the whole group, in
+            // windows of hmax positions of N(y): the lists (y,z) are sorted by
+            // position, so a window is a sub-range of each, found by binary
+            // search; a window is drained by a scan of its positions
+            for (u32 c0 = 0; c0 < da; c0 += WG) {
+                const u32 i = c0 + threadIdx.x;
+                if (i < da) {
+                    const u32 y = ci[ba + i];
+                    if (T[ba + i] > 0 && rp[y + 1] - rp[y] > kl) sh_hub[atomicAdd(&sh_nhub, 1u)] = i;
+                }
+                __syncthreads();
+                const u32 nh = sh_nhub;
+                if (nh) {  // the touched lists' bytes become map positions: clear them
+                    for (u32 w = threadIdx.x; w < WAVES_PER_WG * kl / 2; w += WG)
+                        l_k0[WAVES_PER_WG * kl + w] = 0;
+                    __syncthreads();
+                }
+                for (u32 h = 0; h < nh; h++) {
+                    const u32 say = ba + sh_hub[h], y = ci[say];
+                    const u32 by = rp[y], dy = rp[y + 1] - by;
+                    const TLView tv = tl_view(say, src, ci, rev, T, tl_ptr, tl);
+                    const u32 p0 = lbound(ci + by, dy, a + 1);  // first position with b > a
+                    const u32 nbatch = (tv.len + WAVE - 1) / WAVE;
+                    u64 q = 0, c64 = 0;
+                    for (u32 w0 = p0; w0 < dy; w0 += hmax) {
+                        const u32 w1 = dy - w0 < hmax ? dy : w0 + hmax;
+                        if (threadIdx.x == 0) sh_next = 0;
+                        __syncthreads();
+                        wave_loop(&sh_next, nbatch, [&](u32 bi) {
+                            const u32 kk = bi * WAVE + lane_id();
+                            const uint2 *lp = nullptr;
+                            u32 lo = 0, hi = 0, sw = 0;
+                            if (kk < tv.len) {
+                                const uint2 ez = tv.get(kk);  // (slot(a,z), slot(y,z))
+                                const TLView tw = tl_view(ez.y, src, ci, rev, T, tl_ptr, tl);
+                                // entries with position in [w0, w1)
+                                u32 l = 0, r = tw.len;
+                                while (l < r) {
+                                    const u32 mid = (l + r) >> 1;
+                                    if (tw.get(mid).x < by + w0) l = mid + 1; else r = mid;
+                                }
+                                lo = l;
+                                r = tw.len;
+                                if (w1 < dy) {
+                                    while (l < r) {
+                                        const u32 mid = (l + r) >> 1;
+                                        if (tw.get(mid).x < by + w1) l = mid + 1; else r = mid;
+                                    }
+                                }
+                                hi = r;
+                                lp = tw.p;
+                                sw = tw.swap;
+                            }
+                            const u32 cnt = tv.len - bi * WAVE < WAVE ? tv.len - bi * WAVE : WAVE;
+                            for (u32 j = 0; j < cnt; j++) {
+                                const uint2 *pj =
+                                    (const uint2 *)__shfl((unsigned long long)lp, (int)j, WAVE);
+                                const u32 loj = __shfl(lo, (int)j, WAVE), hij = __shfl(hi, (int)j, WAVE);
+                                const u32 swj = __shfl(sw, (int)j, WAVE);
+                                for (u32 e0 = loj + lane_id(); e0 < hij; e0 += WAVE) {
+                                    const uint2 e = pj[e0];
+                                    nsteps++;
+                                    atomicAdd(&hmap[(swj ? e.y : e.x) - by - w0], 1u);
+                                }
+                            }
+                        });
+                        __syncthreads();
+                        for (u32 p = threadIdx.x; p < w1 - w0; p += WG) {
+                            const u32 kab = hmap[p];
+                            if (!kab) continue;
+                            hmap[p] = 0;
+                            q += wheel_drain(kab, ci[by + w0 + p], vb, P, wide, vacc, c64);
+                        }
+                        __syncthreads();
+                    }
+                    q = GP::sum(q, sh_red);
+                    c64 = GP::sum(c64, sh_red);
+                    if (threadIdx.x == 0) {
+                        Q[say] = q;
+                        atomic_add_u64(&VACC(y, VA_64), c64);
+                    }
+                    if (wave_in_wg() == 0) l68 += q;
+                }
+                __syncthreads();
+                if (threadIdx.x == 0) sh_nhub = 0;
+                __syncthreads();
+            }
+        }
+        // l68 is uniform within each wave (computed from wave or group sums)
         if (lane_id() == 0) atomic_add_u64(&VACC(a, VA_68), l68);
         if (pass_cycles) pass_mark(pass_cycles, 2, t_pass);
-        // pair terms (the records hold 2 e)
+        // pair terms (e2 holds 2 e); a's tb (s-1) comes in the centre pass
         const u32 nt = sh_nt;
         u64 l36 = 0, l50 = 0, l51 = 0, l63 = 0;
         for (u32 t = GP::rank(); t < nt; t += GP::size) {
             const u32 b = P.touched[t];
-            const PairRec &r = P.R[b - vb];
-            const u64 s = r.s;
+            const u64 v = P.sta[b - vb];
+            const u64 s = ps_s(v, wide);
             if (s < 2) continue;
-            const u64 adj = r.adj;
-            const u64 e = r.e2 >> 1;
+            const u64 adj = v >> 63;
+            const u64 ta = wide ? P.ext[b - vb] : (v & PS_TA_MASK);
+            const u64 e = P.e2[b - vb] >> 1;
             const u64 cs2 = c2((i64)s), cs3 = c3((i64)s);
             l36 += cs2 * ((u64)deg[b] - 2);
             l50 += cs3;
-            l51 += (r.tb - adj * s) * (s - 1);
+            l51 -= adj * s * (s - 1);
             l63 += e * (s - 2);
             atomic_add_u64(&VACC(b, VA_36), cs2 * (dega - 2));
             atomic_add_u64(&VACC(b, VA_50), cs3);
-            atomic_add_u64(&VACC(b, VA_51), (r.ta - adj * s) * (s - 1));
+            atomic_add_u64(&VACC(b, VA_51), (ta - adj * s) * (s - 1));
             atomic_add_u64(&VACC(b, VA_63), e * (s - 2));
         }
         l36 = GP::sum(l36, sh_red);
         l50 = GP::sum(l50, sh_red);
-        l51 = GP::sum(l51, sh_red);
         l63 = GP::sum(l63, sh_red);
         if (GP::rank() == 0) {
             atomic_add_u64(&VACC(a, VA_36), l36);
             atomic_add_u64(&VACC(a, VA_50), l50);
-            atomic_add_u64(&VACC(a, VA_51), l51);
             atomic_add_u64(&VACC(a, VA_63), l63);
             sh_next = 0;
         }
         GP::sync();
         if (pass_cycles) pass_mark(pass_cycles, 3, t_pass);
-        // centre terms
+        // centre terms, and a's tb (s-1) wedge by wedge
         wave_loop(&sh_next, da, [&](u32 iy) {
             const u32 say = ba + iy, y = ci[say];
             const u32 by = rp[y], ey = rp[y + 1];
@@ -948,12 +1066,12 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
             u64 a49 = 0, a62 = 0;
             for (u32 s = st0 + lane_id(); s < ey; s += WAVE) {
                 const u32 b = ci[s];
-                const PairRec &r = P.R[b - vb];
-                const u32 sb = r.s;
+                const u64 sb = ps_s(P.sta[b - vb], wide);
                 nsteps++;
                 if (sb >= 2) {
                     a49 += c2((i64)sb - 1);
-                    a62 += r.e2 >> 1;
+                    a62 += P.e2[b - vb] >> 1;
+                    l51 += (u64)T[s] * (sb - 1);
                 }
             }
             a49 = wave_sum_u64(a49);
@@ -963,13 +1081,16 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
                 atomic_add_u64(&VACC(y, VA_62), a62);
             }
         });
+        l51 = GP::sum(l51, sh_red);
+        if (GP::rank() == 0) atomic_add_u64(&VACC(a, VA_51), l51);
         GP::sync();
         for (u32 t = GP::rank(); t < nt; t += GP::size) {
             const u32 b = P.touched[t];
-            PairRec &r = P.R[b - vb];
-            r.s = 0; r.ta = 0; r.tb = 0; r.e2 = 0;
+            P.sta[b - vb] = 0;
+            P.e2[b - vb] = 0;
+            if (wide) P.ext[b - vb] = 0;
         }
-        for (u32 i = GP::rank(); i < da; i += GP::size) P.R[ci[ba + i] - vb].adj = 0;
+        for (u32 i = GP::rank(); i < da; i += GP::size) P.sta[ci[ba + i] - vb] = 0;
         if (pass_cycles) pass_mark(pass_cycles, 4, t_pass);
         if (steps) {  // per-source work, the training target of the scheduler
             u64 tot = GP::sum(nsteps, sh_red);
@@ -1022,11 +1143,6 @@ constexpr int c5_hset_bits() {
 }
 // multiplicative hash onto the C5_HSET slots (the top bits of key * 2^32/phi)
 __device__ inline u32 hset_slot(u32 key) { return (key * 2654435761u) >> (32 - c5_hset_bits()); }
-__device__ inline void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
 __device__ inline bool hset_build(u32 *hs, u32 k, const u64 *out_ptr, const u32 *out_nbr) {
     const u64 b = out_ptr[k], e = out_ptr[k + 1];
     if (e - b > C5_HSET / 2) return false;

@@ -101,10 +101,11 @@ void layout_phase1(Layout &L, u32 n, u64 m, bool relabel = false) {
     L.p1_end = c;
 }
 
-u64 pair_stride(u32 n) {
-    // 32-byte records, touched u32, 4 wave maps + lists u32
-    return align_up(32ull * n, 256) + align_up(4ull * n, 256) +
-           2 * align_up(4ull * WAVES_PER_WG * n, 256) + 256;
+// pair sweep: sta, e2, ext (u64), touched (u32); wave groups add the
+// per-wave global wheel maps and their touched lists (u32, 4 x n each)
+u64 pair_stride(u32 n, bool wave_maps) {
+    return 3 * align_up(8ull * n, 256) + align_up(4ull * n, 256) +
+           (wave_maps ? 2 * align_up(4ull * WAVES_PER_WG * n, 256) : 0) + 256;
 }
 u64 clique_stride(u32 dmax) {
     u64 W = (dmax + 63) / 64;
@@ -148,7 +149,7 @@ void layout_phase2(Layout &L, u32 n, u32 mapn, u64 m, u64 ntri, u32 dmax, int k_
     place(c, L.order, 4ull * n + 4);
     u64 stride = 8ull * mapn + 512;  // 4-cycle maps (and the long-list sort)
     if (k_max >= 5) {
-        u64 ps = pair_stride(mapn);
+        u64 ps = pair_stride(mapn, per_wg > 1);
         if (ps > stride) stride = ps;
     }
     u64 cs = clique_stride(dmax);
@@ -206,16 +207,16 @@ unsigned grid_waves(u64 items) { return grid_for(items * WAVE, WG); }
 struct ZeroRange {
     u64 off, len;
 };
-int zero_ranges(int which, u32 n, ZeroRange *r) {
+int zero_ranges(int which, u32 n, bool wave_maps, ZeroRange *r) {
     const u64 a4 = align_up(4ull * n, 256), a8 = align_up(8ull * n, 256), a1 = align_up(n, 256);
     if (which == 0) {  // 4-cycles: cnt
         r[0] = {0, a4};
         return 1;
     }
-    if (which == 1) {  // pair sweep: records ... then the wave maps K
-        const u64 a32 = align_up(32ull * n, 256);
-        r[0] = {0, a32};
-        r[1] = {a32 + a4, align_up(4ull * WAVES_PER_WG * n, 256)};
+    if (which == 1) {  // pair sweep: sta, e2, ext ... then the wave maps K
+        r[0] = {0, 3 * a8};
+        if (!wave_maps) return 1;
+        r[1] = {3 * a8 + a4, align_up(4ull * WAVES_PER_WG * n, 256)};
         return 2;
     }
     // 5-cycles: Wm, P, CI, (touched), mark
@@ -227,7 +228,7 @@ int zero_ranges(int which, u32 n, ZeroRange *r) {
 int zero_scratch(int which, u32 mapn, unsigned char *scratch, const Layout &L, u32 nwg,
                  hipStream_t s) {
     ZeroRange r[2];
-    int k = zero_ranges(which, mapn, r);
+    int k = zero_ranges(which, mapn, L.per_wg > 1, r);
     for (int i = 0; i < k; i++)
         k_zero_rows<<<grid_for(r[i].len / 8 * nwg, WG), WG, 0, s>>>(scratch + r[i].off, L.stride,
                                                                    r[i].len / 8, nwg);

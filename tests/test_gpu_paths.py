@@ -44,12 +44,23 @@ def _book(k):
     return gg.csr_from_edges(k + 2, u, v)
 
 
+def _hub_over(g):
+    """A new vertex 0 joined to every vertex of g (shifted to 1..n)."""
+    rp, ci = g
+    n = len(rp) - 1
+    src = np.repeat(np.arange(n), np.diff(rp.astype(np.int64)))
+    u = np.concatenate([src + 1, np.zeros(n, np.int64)])
+    v = np.concatenate([ci.astype(np.int64) + 1, np.arange(1, n + 1)])
+    return gg.csr_from_edges(n + 1, u, v)
+
+
 def _tile_graphs():
     return [
         ("er60_dense", lambda: gg.erdos_renyi(60, 0.85, 4101)),   # out-degrees > 32, > 16
         ("er45", lambda: gg.erdos_renyi(45, 0.5, 4102)),
         ("ba120", lambda: gg.barabasi_albert(120, 5, 4103)),      # hubs of degree > 32
         ("chunglu300", lambda: gg.chung_lu(300, 8.0, 2.1, 60.0, 1200, 4104)),
+        ("hub120", lambda: _hub_over(gg.erdos_renyi(120, 0.05, 4105))),  # LDS windows
         ("K30", lambda: gg.complete(30)),
         ("book100", lambda: _book(100)),                          # LDS list sort (65..128)
         ("book200", lambda: _book(200)),                          # bitmap list sort (> 128)
