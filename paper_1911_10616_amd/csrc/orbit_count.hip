@@ -729,6 +729,10 @@ __device__ inline void pass_mark_g(u64 *pc, int k, u64 &t) {
 #ifndef PAIR_KMAP_LDS
 #define PAIR_KMAP_LDS 2048
 #endif
+// list entries a lane loads before it uses them (memory-level parallelism)
+#ifndef UNR
+#define UNR 4
+#endif
 // The pair sweep's per-vertex results go to a compact accumulator of eight
 // words per vertex (one cache line; the combine copies them into the orbit
 // columns) rather than into five lines of the 73-word rows.
@@ -783,6 +787,49 @@ __device__ inline u64 wheel_drain(u32 kab, u32 b, u32 vb, const PairState &P, bo
     return v;
 }
 
+// Flat walk over up to 64 list parts held by the lanes of a wave: lane k
+// holds part k (n_k entries, and whatever the caller stores for it in the
+// wave's FlatLds).  The wave runs through the flat indices f = lane + 64 i,
+// UNR per lane per step, so a long part is read with coalesced loads and
+// short parts are read in parallel by different lanes -- a lane never waits
+// for one list to end before loading from the next.  F(jv, ov, valid)
+// receives UNR (part, offset) pairs; the parts of one lane only increase.
+struct FlatLds {
+    u32 pre[WAVE + 1];  // exclusive prefix sums of n_k; pre[64] = total
+    u32 aux[WAVE];      // per part: caller data
+    u64 ptr[WAVE];      // per part: caller data (a list base address)
+};
+template <typename F>
+__device__ inline void flat_walk(FlatLds &L, u32 n_mine, F f) {
+    const u32 lane = lane_id();
+    u32 x = n_mine;
+    for (int off = 1; off < WAVE; off <<= 1) {
+        const u32 t = __shfl_up(x, off, WAVE);
+        if ((int)lane >= off) x += t;
+    }
+    L.pre[lane + 1] = x;
+    if (lane == 0) L.pre[0] = 0;
+    const u32 total = __shfl(x, WAVE - 1, WAVE);
+    wave_sync();
+    u32 j = 0;
+    for (u32 f0 = lane; f0 < total; f0 += UNR * WAVE) {
+        u32 jv[UNR], ov[UNR];
+        bool ok[UNR];
+#pragma unroll
+        for (int k = 0; k < UNR; k++) {
+            const u32 fk = f0 + k * WAVE;
+            ok[k] = fk < total;
+            if (ok[k]) {
+                while (fk >= L.pre[j + 1]) j++;
+                jv[k] = j;
+                ov[k] = fk - L.pre[j];
+            }
+        }
+        f(jv, ov, ok);
+    }
+    wave_sync();
+}
+
 template <class GP>
 __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, const u32 *src,
                                              const u32 *rev, const u32 *deg, const u32 *T,
@@ -800,6 +847,8 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
     __shared__ u32 sh_ntk[WAVES_PER_WG];
     __shared__ u64 sh_red[WAVES_PER_WG];
     __shared__ u32 sh_hub[WG], sh_nhub;  // workgroup groups: this chunk's arcs to hubs
+    __shared__ FlatLds sh_flat[WAVES_PER_WG];
+    FlatLds &FL = sh_flat[wave_in_wg()];
     // dynamic LDS: per-wave wheel maps of kl positions (u32) and touched
     // lists (u16), kl <= PAIR_KMAP_LDS; in workgroup groups the same bytes
     // also serve as one map of hmax = 6 kl positions for the hub arcs
@@ -811,6 +860,7 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
     PairState P = pair_state(scratch + GP::global_id() * stride, mapn, kWaveGroups);
     u32 *Kw = kWaveGroups ? P.K + (u64)wave_in_wg() * mapn : nullptr;
     u32 *tkw = kWaveGroups ? P.tk + (u64)wave_in_wg() * mapn : nullptr;
+    const u32 lane = lane_id();
     // every thread of the workgroup clears its share, then all wait (the
     // slices belong to different waves)
     for (u32 i = threadIdx.x; i < hmax; i += WG) hmap[i] = 0;
@@ -830,24 +880,42 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
         if (GP::rank() == 0) { sh_nt = 0; sh_next = 0; }
         GP::sync();
         if (pass_cycles) pass_mark(pass_cycles, 0, t_pass);
-        // wedges a - y - b, b > a: s and ta of the pair (a, b)
+        // wedges a - y - b, b > a: s and ta of the pair (a, b); UNR entries
+        // per lane per step, whose loads and atomics are independent
         wave_loop(&sh_next, da, [&](u32 iy) {
             const u32 say = ba + iy, y = ci[say];
             const u64 tay = T[say];
             const u32 by = rp[y], ey = rp[y + 1];
             const u32 st0 = by + lbound(ci + by, ey - by, a + 1);
-            for (u32 s = st0 + lane_id(); s < ey; s += WAVE) {
-                const u32 b = ci[s];
-                nsteps++;
-                u64 old;
-                if (!wide) {
-                    old = atomicAdd(&P.sta[b - vb], (1ull << PS_SHIFT) | tay) & ~PS_ADJ;
-                    old >>= PS_SHIFT;
-                } else {
-                    old = atomicAdd(&P.sta[b - vb], 1ull) & ~PS_ADJ;
-                    atomicAdd(&P.ext[b - vb], tay);
+            for (u32 s0 = st0 + lane; s0 < ey; s0 += UNR * WAVE) {
+                u32 bv[UNR];
+                u64 old[UNR];
+#pragma unroll
+                for (int k = 0; k < UNR; k++) {
+                    const u32 s = s0 + k * WAVE;
+                    bv[k] = s < ey ? ci[s] : UNSET;
                 }
-                if (old == 0) P.touched[atomicAdd(&sh_nt, 1u)] = b;
+                if (!wide) {
+#pragma unroll
+                    for (int k = 0; k < UNR; k++)
+                        if (bv[k] != UNSET)
+                            old[k] = atomicAdd(&P.sta[bv[k] - vb], (1ull << PS_SHIFT) | tay);
+#pragma unroll
+                    for (int k = 0; k < UNR; k++) old[k] = (old[k] & ~PS_ADJ) >> PS_SHIFT;
+                } else {
+#pragma unroll
+                    for (int k = 0; k < UNR; k++)
+                        if (bv[k] != UNSET) {
+                            old[k] = atomicAdd(&P.sta[bv[k] - vb], 1ull) & ~PS_ADJ;
+                            atomicAdd(&P.ext[bv[k] - vb], tay);
+                        }
+                }
+#pragma unroll
+                for (int k = 0; k < UNR; k++)
+                    if (bv[k] != UNSET) {
+                        nsteps++;
+                        if (old[k] == 0) P.touched[atomicAdd(&sh_nt, 1u)] = bv[k];
+                    }
             }
         });
         GP::sync();
@@ -865,8 +933,9 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
         // the arc's end.  The map of (a, y) is indexed by b's position in
         // N(y): a wave's LDS map when d(y) <= kl; else, in workgroup groups,
         // the whole group's LDS map in windows of hmax positions (below), and
-        // in wave groups the wave's global map.
-        if (lane_id() == 0) sh_ntk[wave_in_wg()] = 0;
+        // in wave groups the wave's global map.  The lists (y,z) of 64 z at
+        // a time are walked flat.
+        if (lane == 0) sh_ntk[wave_in_wg()] = 0;
         u64 l68 = 0;
         wave_loop(&sh_next, da, [&](u32 iy) {
             const u32 say = ba + iy, y = ci[say];
@@ -882,50 +951,50 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
             const u32 ya = by + lbound(ci + by, dy, a + 1);
             for (u32 k0 = 0; k0 < tv.len; k0 += WAVE) {
                 // each lane locates the part b > a of one list (y,z) ...
-                const u32 kk = k0 + lane_id();
-                const uint2 *lp = nullptr;
-                u32 lo = 0, len = 0, sw = 0;
+                const u32 kk = k0 + lane;
+                u32 cnt = 0;
                 if (kk < tv.len) {
                     const uint2 ez = tv.get(kk);  // (slot(a,z), slot(y,z))
                     const TLView tw = tl_view(ez.y, src, ci, rev, T, tl_ptr, tl);
-                    u32 hi = tw.len;
+                    u32 lo = 0, hi = tw.len;
                     while (lo < hi) {
                         const u32 mid = (lo + hi) >> 1;
                         if (tw.get(mid).x < ya) lo = mid + 1; else hi = mid;
                     }
-                    lp = tw.p;
-                    len = tw.len;
-                    sw = tw.swap;
+                    cnt = tw.len - lo;
+                    FL.ptr[lane] = (u64)(tw.p + lo);
+                    FL.aux[lane] = tw.swap;
                 }
-                // ... then the wave walks those parts one list at a time
-                const u32 cnt = tv.len - k0 < WAVE ? tv.len - k0 : WAVE;
-                for (u32 j = 0; j < cnt; j++) {
-                    const uint2 *pj = (const uint2 *)__shfl((unsigned long long)lp, (int)j, WAVE);
-                    const u32 loj = __shfl(lo, (int)j, WAVE), lenj = __shfl(len, (int)j, WAVE);
-                    const u32 swj = __shfl(sw, (int)j, WAVE);
-                    for (u32 q = loj + lane_id(); q < lenj; q += WAVE) {
-                        const uint2 e = pj[q];
-                        const u32 pos = (swj ? e.y : e.x) - by;  // slot(y,b) - rp[y]
+                // ... then the wave walks those parts flat
+                flat_walk(FL, cnt, [&](const u32 *jv, const u32 *ov, const bool *ok) {
+                    uint2 ev[UNR];
+#pragma unroll
+                    for (int k = 0; k < UNR; k++)
+                        if (ok[k]) ev[k] = ((const uint2 *)FL.ptr[jv[k]])[ov[k]];
+#pragma unroll
+                    for (int k = 0; k < UNR; k++) {
+                        if (!ok[k]) continue;
+                        const u32 pos = (FL.aux[jv[k]] ? ev[k].y : ev[k].x) - by;  // slot(y,b) - rp[y]
                         nsteps++;
-                        u32 old = atomicAdd(&kc[pos], 1u);
+                        const u32 old = atomicAdd(&kc[pos], 1u);
                         if (old == 0) {
                             const u32 t = atomicAdd(ntk, 1u);
                             if (inl) tl_l[t] = (unsigned short)pos; else tkw[t] = pos;
                         }
                     }
-                }
+                });
             }
             wave_sync();
             const u32 m = *ntk;
             u64 q = 0, c64 = 0;
-            for (u32 t = lane_id(); t < m; t += WAVE) {
+            for (u32 t = lane; t < m; t += WAVE) {
                 const u32 pos = inl ? (u32)tl_l[t] : tkw[t];
                 const u32 kab = atomicExch(&kc[pos], 0u);
                 q += wheel_drain(kab, ci[by + pos], vb, P, wide, vacc, c64);
             }
             q = wave_sum_u64(q);
             c64 = wave_sum_u64(c64);
-            if (lane_id() == 0) {
+            if (lane == 0) {
                 Q[say] = q;
                 atomic_add_u64(&VACC(y, VA_64), c64);
                 *ntk = 0;
@@ -964,9 +1033,8 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
                         if (threadIdx.x == 0) sh_next = 0;
                         __syncthreads();
                         wave_loop(&sh_next, nbatch, [&](u32 bi) {
-                            const u32 kk = bi * WAVE + lane_id();
-                            const uint2 *lp = nullptr;
-                            u32 lo = 0, hi = 0, sw = 0;
+                            const u32 kk = bi * WAVE + lane;
+                            u32 cnt = 0;
                             if (kk < tv.len) {
                                 const uint2 ez = tv.get(kk);  // (slot(a,z), slot(y,z))
                                 const TLView tw = tl_view(ez.y, src, ci, rev, T, tl_ptr, tl);
@@ -976,7 +1044,7 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
                                     const u32 mid = (l + r) >> 1;
                                     if (tw.get(mid).x < by + w0) l = mid + 1; else r = mid;
                                 }
-                                lo = l;
+                                const u32 lo = l;
                                 r = tw.len;
                                 if (w1 < dy) {
                                     while (l < r) {
@@ -984,22 +1052,22 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
                                         if (tw.get(mid).x < by + w1) l = mid + 1; else r = mid;
                                     }
                                 }
-                                hi = r;
-                                lp = tw.p;
-                                sw = tw.swap;
+                                cnt = r - lo;
+                                FL.ptr[lane] = (u64)(tw.p + lo);
+                                FL.aux[lane] = tw.swap;
                             }
-                            const u32 cnt = tv.len - bi * WAVE < WAVE ? tv.len - bi * WAVE : WAVE;
-                            for (u32 j = 0; j < cnt; j++) {
-                                const uint2 *pj =
-                                    (const uint2 *)__shfl((unsigned long long)lp, (int)j, WAVE);
-                                const u32 loj = __shfl(lo, (int)j, WAVE), hij = __shfl(hi, (int)j, WAVE);
-                                const u32 swj = __shfl(sw, (int)j, WAVE);
-                                for (u32 e0 = loj + lane_id(); e0 < hij; e0 += WAVE) {
-                                    const uint2 e = pj[e0];
-                                    nsteps++;
-                                    atomicAdd(&hmap[(swj ? e.y : e.x) - by - w0], 1u);
-                                }
-                            }
+                            flat_walk(FL, cnt, [&](const u32 *jv, const u32 *ov, const bool *ok) {
+                                uint2 ev[UNR];
+#pragma unroll
+                                for (int k = 0; k < UNR; k++)
+                                    if (ok[k]) ev[k] = ((const uint2 *)FL.ptr[jv[k]])[ov[k]];
+#pragma unroll
+                                for (int k = 0; k < UNR; k++)
+                                    if (ok[k]) {
+                                        nsteps++;
+                                        atomicAdd(&hmap[(FL.aux[jv[k]] ? ev[k].y : ev[k].x) - by - w0], 1u);
+                                    }
+                            });
                         });
                         __syncthreads();
                         for (u32 p = threadIdx.x; p < w1 - w0; p += WG) {
@@ -1024,7 +1092,7 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
             }
         }
         // l68 is uniform within each wave (computed from wave or group sums)
-        if (lane_id() == 0) atomic_add_u64(&VACC(a, VA_68), l68);
+        if (lane == 0) atomic_add_u64(&VACC(a, VA_68), l68);
         if (pass_cycles) pass_mark(pass_cycles, 2, t_pass);
         // pair terms (e2 holds 2 e); a's tb (s-1) comes in the centre pass
         const u32 nt = sh_nt;
@@ -1064,19 +1132,36 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
             const u32 by = rp[y], ey = rp[y + 1];
             const u32 st0 = by + lbound(ci + by, ey - by, a + 1);
             u64 a49 = 0, a62 = 0;
-            for (u32 s = st0 + lane_id(); s < ey; s += WAVE) {
-                const u32 b = ci[s];
-                const u64 sb = ps_s(P.sta[b - vb], wide);
-                nsteps++;
-                if (sb >= 2) {
-                    a49 += c2((i64)sb - 1);
-                    a62 += P.e2[b - vb] >> 1;
-                    l51 += (u64)T[s] * (sb - 1);
+            for (u32 s0 = st0 + lane; s0 < ey; s0 += UNR * WAVE) {
+                u32 bv[UNR];
+                u64 tv[UNR], sv[UNR], ev2[UNR];
+#pragma unroll
+                for (int k = 0; k < UNR; k++) {
+                    const u32 s = s0 + k * WAVE;
+                    bv[k] = s < ey ? ci[s] : UNSET;
+                    tv[k] = s < ey ? T[s] : 0;
+                }
+#pragma unroll
+                for (int k = 0; k < UNR; k++)
+                    if (bv[k] != UNSET) {
+                        sv[k] = P.sta[bv[k] - vb];
+                        ev2[k] = P.e2[bv[k] - vb];
+                    }
+#pragma unroll
+                for (int k = 0; k < UNR; k++) {
+                    if (bv[k] == UNSET) break;
+                    const u64 sb = ps_s(sv[k], wide);
+                    nsteps++;
+                    if (sb >= 2) {
+                        a49 += c2((i64)sb - 1);
+                        a62 += ev2[k] >> 1;
+                        l51 += tv[k] * (sb - 1);
+                    }
                 }
             }
             a49 = wave_sum_u64(a49);
             a62 = wave_sum_u64(a62);
-            if (lane_id() == 0) {
+            if (lane == 0) {
                 atomic_add_u64(&VACC(y, VA_49), a49);
                 atomic_add_u64(&VACC(y, VA_62), a62);
             }
