@@ -15,6 +15,8 @@ Parity status of each function (what pins it is listed in the tests):
   noninduced_counts   pinned (paper's 4-vertex lemma equations, eq. orb26,
                       brute-force injective maps, Fig. A)
   rooted_counts       pinned against induced_counts (same definition)
+  edge_counts         pinned (Lemma 4edgeorbit equations on brute-force T, C4,
+                      K4; brute-force injective maps; closed forms)
   transform_matrix    pinned against Fig. A (with the row-5 erratum)
   overflow_flags      the overflow reading of integer width (the paper is
                       silent on it): pinned by brute-force homomorphism
@@ -31,6 +33,7 @@ import numpy as np
 
 NORB = 73
 NGRAPHLET = 30
+NEORB = 12
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "orbit_oracle.c")
 _LIB = os.path.join(_HERE, "liborbit_oracle.so")
@@ -68,6 +71,8 @@ def _load():
                                              ctypes.c_uint32, ctypes.c_uint64, u64p,
                                              ctypes.POINTER(ctypes.c_uint8), ctypes.c_int]
         lib.oracle_rooted_counts.restype = ctypes.c_int
+        lib.oracle_edge_counts.argtypes = [u32p, u32p, ctypes.c_uint32, u64p, ctypes.c_int]
+        lib.oracle_edge_counts.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -137,6 +142,21 @@ def noninduced_counts(row_ptr, col_idx, kmax: int = 5, threads: int = 1) -> np.n
     if rc:
         raise RuntimeError(f"oracle failed: {rc}")
     return out[:n]
+
+
+def edge_counts(row_ptr, col_idx, threads: int = 1) -> np.ndarray:
+    """uint64[2m, 12]: non-induced edge orbit counts E_0..E_11 of every CSR
+    slot (u, v) -- for an edge orbit whose two endpoint vertex orbits
+    differ, the count with u in the endpoint orbit of larger index
+    (Definition edge-orbit; matches as defined after Fig. edge_orbits)."""
+    rp, ci, n = _graph(row_ptr, col_idx)
+    m2 = int(rp[-1]) if n >= 0 else 0
+    out = np.zeros((max(m2, 1), NEORB), np.uint64)
+    rc = _load().oracle_edge_counts(_ptr(rp, ctypes.c_uint32), _ptr(ci, ctypes.c_uint32), n,
+                                    _ptr(out, ctypes.c_uint64), threads)
+    if rc:
+        raise RuntimeError(f"oracle failed: {rc}")
+    return out[:m2]
 
 
 def rooted_counts(row_ptr, col_idx, roots, kmax: int = 5, budget: int = 0, threads: int = 1):

@@ -28,6 +28,14 @@
  *     edge subset is classified with the same table.
  *   - Rooted counts: induced counts of one vertex only, enumerating the
  *     connected subsets that contain it, with an optional subset budget.
+ *   - Edge orbit counts E_0..E_11 (Definition edge-orbit; the matches of
+ *     an edge orbit in the definition after Fig. edge_orbits): edge
+ *     orbits are the classes of the automorphism relation on the edges of
+ *     the 3- and 4-vertex patterns, labelled from Fig. edge_orbits; every
+ *     non-induced copy of such a pattern (a connected spanning edge subset
+ *     of a connected 3- or 4-subset) adds one to each of its edges, at the
+ *     slot (u,v) whose u lies in the endpoint orbit of larger index, and
+ *     at both slots when the two endpoint orbits are the same.
  *
  * All counts are uint64 and wrap modulo 2^64.
  */
@@ -86,6 +94,17 @@ static const pattern_t PATTERNS[NGRAPHLET] = {
     /* H29 */ {5, 10, {{1,2},{1,3},{1,4},{1,5},{2,3},{2,4},{2,5},{3,4},{3,5},{4,5}}, 1, {{5,72}}},
 };
 
+/* ---- edge orbit transcription (Fig. edge_orbits) --------------------------
+ * For each printed edge-orbit label 0..11: the pattern and the TikZ node ids
+ * of the edge the label is drawn beside.  The figure's drawings of H1..H8
+ * number their nodes as the figure of vertex orbits does.                  */
+#define NEORB 12
+static const int EDGE_LABELS[NEORB][3] = {
+    /* label: pattern, node, node */
+    {1, 2, 3}, {2, 1, 3}, {3, 3, 4}, {3, 2, 3}, {4, 3, 4}, {5, 3, 4},
+    {6, 1, 2}, {6, 3, 4}, {6, 2, 4}, {7, 2, 4}, {7, 1, 4}, {8, 1, 4},
+};
+
 /* ---- derived tables ---------------------------------------------------- */
 static int g_ready = 0;
 static int g_status = 0;               /* 0 ok; <0 transcription inconsistent */
@@ -98,6 +117,9 @@ static int g_pair[MAXK][MAXK];
 /* LUT per k: graphlet id (or -1 if disconnected) and orbit of each position */
 static signed char g_lut_graphlet[MAXK + 1][1024];
 static signed char g_lut_orbit[MAXK + 1][1024][MAXK];
+/* edge orbit of an edge whose endpoints lie in vertex orbits (hi, lo),
+ * hi >= lo, of a 3- or 4-vertex pattern; -1 if no edge orbit has them */
+static signed char g_edge_label[15][15];
 
 static int next_perm(int *a, int k) {
     int i = k - 2;
@@ -118,6 +140,56 @@ static int pattern_mask(const pattern_t *p, const int *pos_of_node) {
         mask |= 1 << g_pair[lo][hi];
     }
     return mask;
+}
+
+/* Edge orbits of patterns H1..H8: classes of edges under the automorphisms
+ * (permutations preserving the edge set), each labelled from the figure;
+ * then the (endpoint orbit, endpoint orbit) -> label table, which must be
+ * unambiguous for the classification by vertex orbits to be valid. */
+static void build_edge_tables(void) {
+    memset(g_edge_label, -1, sizeof g_edge_label);
+    for (int h = 1; h <= 8; h++) {
+        const pattern_t *p = &PATTERNS[h];
+        int k = p->k;
+        int base = pattern_mask(p, (int[]){0, 1, 2, 3, 4});
+        int cls[10];  /* class of each pattern edge (index into p->e) */
+        for (int e = 0; e < p->ne; e++) cls[e] = e;
+        int perm[MAXK] = {0, 1, 2, 3, 4};
+        do {
+            if (pattern_mask(p, perm) != base) continue;
+            for (int e = 0; e < p->ne; e++) {
+                int x = perm[p->e[e][0] - 1], y = perm[p->e[e][1] - 1];
+                for (int f = 0; f < p->ne; f++) {
+                    int a = p->e[f][0] - 1, b = p->e[f][1] - 1;
+                    if ((a == x && b == y) || (a == y && b == x)) {
+                        int c1 = cls[e], c2 = cls[f];
+                        int lo = c1 < c2 ? c1 : c2, hi = c1 < c2 ? c2 : c1;
+                        for (int g = 0; g < p->ne; g++) if (cls[g] == hi) cls[g] = lo;
+                    }
+                }
+            }
+        } while (next_perm(perm, k));
+        int label_of_class[10];
+        for (int e = 0; e < p->ne; e++) label_of_class[e] = -1;
+        for (int l = 0; l < NEORB; l++) {
+            if (EDGE_LABELS[l][0] != h) continue;
+            int a = EDGE_LABELS[l][1], b = EDGE_LABELS[l][2], found = -1;
+            for (int e = 0; e < p->ne; e++)
+                if ((p->e[e][0] == a && p->e[e][1] == b) || (p->e[e][0] == b && p->e[e][1] == a))
+                    found = e;
+            if (found < 0) { g_status = -7; continue; }
+            if (label_of_class[cls[found]] != -1) g_status = -8;
+            label_of_class[cls[found]] = l;
+        }
+        for (int e = 0; e < p->ne; e++) {
+            int l = label_of_class[cls[e]];
+            if (l < 0) { g_status = -9; continue; }
+            int oa = g_node_orbit[h][p->e[e][0] - 1], ob = g_node_orbit[h][p->e[e][1] - 1];
+            int hi = oa > ob ? oa : ob, lo = oa > ob ? ob : oa;
+            if (g_edge_label[hi][lo] != -1 && g_edge_label[hi][lo] != l) g_status = -10;
+            g_edge_label[hi][lo] = (signed char)l;
+        }
+    }
 }
 
 static void build_tables(void) {
@@ -184,6 +256,7 @@ static void build_tables(void) {
         } while (next_perm(pos, k));
     }
     for (int o = 0; o < NORB; o++) if (g_orbit_graphlet[o] < 0) g_status = -6;
+    build_edge_tables();
     g_ready = 1;
 }
 
@@ -233,7 +306,34 @@ typedef struct {
     uint64_t budget;           /* 0 = unlimited */
     uint64_t visited;
     int exhausted;
+    uint64_t *ecounts;         /* non-induced mode: 2m x 12 edge orbit counts, or NULL */
+    int eerr;                  /* an edge whose endpoint orbits name no edge orbit */
 } esu_t;
+
+/* slot of v in the neighbour list of u (v must be a neighbour) */
+static uint64_t slot_of(const graph_t *g, uint32_t u, uint32_t v) {
+    uint32_t lo = g->rp[u], hi = g->rp[u + 1];
+    while (lo < hi) {
+        uint32_t mid = lo + (hi - lo) / 2;
+        if (g->ci[mid] < v) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+/* one non-induced copy (edge mask sub of positions 0..k-1 of s, pattern of
+ * 3 or 4 vertices): one count for every edge, at its oriented slot(s) */
+static void count_copy_edges(esu_t *st, const uint32_t *s, int k, int sub) {
+    for (int j = 1; j < k; j++)
+        for (int i = 0; i < j; i++) {
+            if (!(sub >> g_pair[i][j] & 1)) continue;
+            int oi = g_lut_orbit[k][sub][i], oj = g_lut_orbit[k][sub][j];
+            int hi = oi > oj ? oi : oj, lo = oi > oj ? oj : oi;
+            int l = (hi < 15) ? g_edge_label[hi][lo] : -1;
+            if (l < 0) { st->eerr = 1; continue; }
+            if (oi >= oj) st->ecounts[slot_of(st->g, s[i], s[j]) * NEORB + l]++;
+            if (oj >= oi) st->ecounts[slot_of(st->g, s[j], s[i]) * NEORB + l]++;
+        }
+}
 
 static int64_t key_of(const esu_t *st, uint32_t v) {
     return (st->root_first && v == st->root) ? -1 : (int64_t)v;
@@ -254,7 +354,9 @@ static void classify(esu_t *st, const uint32_t *s, int k) {
     }
     /* non-induced: every connected spanning edge subset of G[s] */
     for (int sub = mask;; sub = (sub - 1) & mask) {
-        if (g_lut_graphlet[k][sub] >= 0) {
+        if (g_lut_graphlet[k][sub] >= 0 && st->ecounts && k >= 3 && k <= 4)
+            count_copy_edges(st, s, k, sub);
+        if (g_lut_graphlet[k][sub] >= 0 && st->counts) {
             if (st->rooted) {
                 for (int i = 0; i < k; i++)
                     if (s[i] == st->root) st->counts[g_lut_orbit[k][sub][i]]++;
@@ -448,4 +550,48 @@ int oracle_rooted_counts(const uint32_t *rp, const uint32_t *ci, uint32_t n, int
         complete[r] = st.exhausted ? 0 : 1;
     }
     return 0;
+}
+
+/* Non-induced edge orbit counts E_0..E_11 of every slot of the CSR:
+ * ecounts[slot * 12 + i] = E_i<u,v> for slot (u,v), u the endpoint in the
+ * orbit of larger index (both slots hold E_i when the endpoint orbits are
+ * equal).  Returns -12 if a copy has an edge no edge orbit describes. */
+int oracle_edge_counts(const uint32_t *rp, const uint32_t *ci, uint32_t n, uint64_t *ecounts,
+                       int nthreads) {
+    ensure_tables();
+    if (g_status) return g_status;
+    graph_t g = {rp, ci, n};
+    const size_t len = (size_t)rp[n] * NEORB;
+    memset(ecounts, 0, sizeof(uint64_t) * len);
+    int nt = nthreads > 0 ? nthreads : 1;
+    int err = 0;
+#ifndef _OPENMP
+    nt = 1;
+#endif
+    if (nt == 1) {
+        for (uint32_t v = 0; v < n; v++) {
+            esu_t st = {&g, 4, v, 0, 1, NULL, 0, 0, 0, 0, ecounts, 0};
+            esu_root(&st);
+            err |= st.eerr;
+        }
+        return err ? -12 : 0;
+    }
+#ifdef _OPENMP
+    uint64_t *part = (uint64_t *)calloc((size_t)nt * len + 1, sizeof(uint64_t));
+    if (!part) return -11;
+#pragma omp parallel num_threads(nt) reduction(| : err)
+    {
+        uint64_t *mine = part + (size_t)omp_get_thread_num() * len;
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t v = 0; v < (int64_t)n; v++) {
+            esu_t st = {&g, 4, (uint32_t)v, 0, 1, NULL, 0, 0, 0, 0, mine, 0};
+            esu_root(&st);
+            err |= st.eerr;
+        }
+    }
+    for (int t = 0; t < nt; t++)
+        for (size_t i = 0; i < len; i++) ecounts[i] += part[(size_t)t * len + i];
+    free(part);
+#endif
+    return err ? -12 : 0;
 }

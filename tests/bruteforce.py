@@ -161,3 +161,63 @@ def noninduced(row_ptr, col_idx, kmax=5):
                     for i in range(k):
                         out[S[i], orb[i]] += 1
     return out
+
+
+# Edge orbits of the 3- and 4-vertex patterns (Fig. edge_orbits): the
+# printed label of each edge orbit and one edge of it (pattern index into
+# PATTERNS, 1-based node ids of that figure).  Classes follow from brute-force
+# automorphisms of the pattern's edge set.
+EDGE_LABELS = [(1, (2, 3)), (2, (1, 3)), (3, (3, 4)), (3, (2, 3)), (4, (3, 4)), (5, (3, 4)),
+               (6, (1, 2)), (6, (3, 4)), (6, (2, 4)), (7, (2, 4)), (7, (1, 4)), (8, (1, 4))]
+
+
+def edge_orbit_classes():
+    """{pattern h: (k, edges, {frozenset edge: label}, orbit per node)}."""
+    po = pattern_orbits()
+    out = {}
+    for h in range(1, 9):
+        k, es, orb, _ = po[h]
+        edges = sorted(tuple(sorted(e)) for e in es)
+        auts = [p for p in permutations(range(k))
+                if _eset((p[a], p[b]) for a, b in edges) == es]
+        label = {}
+        for lab, (hh, (a, b)) in enumerate(EDGE_LABELS):
+            if hh != h:
+                continue
+            rep = (a - 1, b - 1)
+            for p in auts:
+                label[frozenset((p[rep[0]], p[rep[1]]))] = lab
+        assert set(label) == set(es), h
+        out[h] = (k, edges, label, orb)
+    return out
+
+
+def edge_orbit_counts(row_ptr, col_idx):
+    """int64[2m, 12]: E_i<u,v> at slot (u, v) from injective maps of every
+    3- and 4-vertex pattern into the graph (edges preserved), divided by the
+    pattern's automorphism count; u is the endpoint in the orbit of larger
+    index, and both slots count when the endpoint orbits are equal."""
+    adj = adjacency_sets(row_ptr, col_idx)
+    n = len(adj)
+    rp = [int(x) for x in row_ptr]
+    slot = {}
+    for u in range(n):
+        for i, v in enumerate(int(c) for c in col_idx[rp[u]:rp[u + 1]]):
+            slot[(u, v)] = rp[u] + i
+    out = np.zeros((rp[-1], 12), np.int64)
+    for h, (k, edges, label, orb) in edge_orbit_classes().items():
+        es = _eset(edges)
+        aut = sum(1 for p in permutations(range(k)) if _eset((p[a], p[b]) for a, b in edges) == es)
+        acc = np.zeros_like(out)
+        for f in permutations(range(n), k):
+            if not all(f[b] in adj[f[a]] for a, b in edges):
+                continue
+            for a, b in edges:
+                lab = label[frozenset((a, b))]
+                if orb[a] >= orb[b]:
+                    acc[slot[(f[a], f[b])], lab] += 1
+                if orb[b] >= orb[a]:
+                    acc[slot[(f[b], f[a])], lab] += 1
+        assert (acc % aut == 0).all()
+        out += acc // aut
+    return out

@@ -392,3 +392,64 @@ def test_overflow_flags_star():
     f = oracle.overflow_flags(rp, ci)
     assert f[0] == 1 and f[1:].sum() == 0
     assert comb(150_000, 4) > 2 ** 64
+
+
+# ------------------------------------------------------------ edge orbits
+
+def _lemma_4edgeorbit(rp, ci):
+    """E_0..E_11 per slot from the equations of Lemma 4edgeorbit, with T(e),
+    T(u), C4(e) and K4(e) counted by brute force."""
+    adj = bf.adjacency_sets(rp, ci)
+    n = len(adj)
+    d = [len(a) for a in adj]
+    T = lambda u, v: len(adj[u] & adj[v])
+    Tv = [sum(1 for v in adj[u] for x in adj[u] if v < x and x in adj[v]) for u in range(n)]
+
+    def c4(u, v):  # 4-cycles u - v - x - y - u
+        return sum(1 for x in adj[v] if x != u for y in adj[x] & adj[u] if y not in (u, v))
+
+    def k4(u, v):
+        com = sorted(adj[u] & adj[v])
+        return sum(1 for i, x in enumerate(com) for y in com[i + 1:] if y in adj[x])
+
+    out = []
+    for u in range(n):
+        for v in (int(c) for c in ci[rp[u]:rp[u + 1]]):
+            t = T(u, v)
+            n1 = sum(d[x] - 1 for x in adj[u] if x != v)
+            out.append([d[u] - 1, t, n1 - t, (d[u] - 1) * (d[v] - 1) - t, comb(d[u] - 1, 2),
+                        c4(u, v), Tv[u] - t, sum(d[x] - 2 for x in adj[u] & adj[v]),
+                        t * (d[u] - 2), sum(T(u, x) - 1 for x in adj[u] & adj[v]), comb(t, 2),
+                        k4(u, v)])
+    return np.array(out, np.int64).reshape(-1, 12)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_edge_orbits_lemma(seed):
+    graphs = [gg.erdos_renyi(10, [0.3, 0.5, 0.8][seed % 3], 700 + seed),
+              gg.barabasi_albert(14, 3, 710 + seed)]
+    for rp, ci in graphs:
+        np.testing.assert_array_equal(oracle.edge_counts(rp, ci).astype(np.int64),
+                                      _lemma_4edgeorbit(rp, ci))
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_edge_orbits_brute_force(seed):
+    rp, ci = gg.erdos_renyi(7, [0.4, 0.6, 0.9][seed], 720 + seed)
+    np.testing.assert_array_equal(oracle.edge_counts(rp, ci).astype(np.int64),
+                                  bf.edge_orbit_counts(rp, ci))
+
+
+@pytest.mark.parametrize("n", [4, 5, 7])
+def test_edge_orbits_complete_and_cycle(n):
+    """K_n: every edge in n-2 triangles, (n-2)(n-3) 4-cycles, C(n-2,2)
+    4-cliques; C_n (n >= 5): only the path orbits, once each."""
+    rp, ci = gg.complete(n)
+    a, b2 = n - 2, comb(n - 2, 2)
+    exp = [a, a, a * (a - 1), a * (a - 1), b2, a * (a - 1), b2, a * (a - 1), a * (a - 1),
+           a * (a - 1), b2, b2]
+    assert (oracle.edge_counts(rp, ci).astype(np.int64) == np.array(exp)).all()
+    if n >= 5:
+        rp, ci = gg.cycle(n)
+        exp = [1, 0, 1, 1] + [0] * 8
+        assert (oracle.edge_counts(rp, ci).astype(np.int64) == np.array(exp)).all()
