@@ -127,6 +127,24 @@ int orbit_num_orbits(int k_max);
 int orbit_count(const uint32_t *row_ptr, const uint32_t *col_idx, uint32_t n, uint64_t m,
                 int k_max, uint64_t *counts);
 
+/* Edge orbit counts of the 3- and 4-vertex patterns (Definition edge-orbit,
+ * Fig. edge_orbits, computed by the equations of Lemma 4edgeorbit) together
+ * with the vertex counts of orbit_count_ex: edge_counts (DEVICE, 2m x 12
+ * uint64) receives, for every CSR slot s = (u, v),
+ *   edge_counts[s * 12 + i] = E_i<u,v>,  i = 0..11,
+ * the number of non-induced copies of the edge orbit's pattern in which
+ * the edge (u,v) lies in edge orbit i with u in the endpoint vertex orbit of
+ * larger index; for an edge orbit whose two endpoint orbits coincide (1, 3,
+ * 5, 7, 10, 11) both slots of the edge hold the same count.  k_max must be
+ * 4 or 5 (counts has K = 15 or 73 columns); the workspace is that of
+ * orbit_count_ex with the same k_max (orbit_workspace_query).  Not with
+ * ORB_RELABEL (ORB_E_INVALID_ARG).  Values wrap modulo 2^64 like the
+ * vertex counts. */
+int orbit_count_edges(const uint32_t *row_ptr, const uint32_t *col_idx, uint32_t n, uint64_t m,
+                      int k_max, uint64_t *counts, uint64_t *edge_counts, void *workspace,
+                      uint64_t ws_bytes, uint64_t *ws_required, void *stream,
+                      const orb_opts *opts);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the count
  * of orbit_count_ex with default options, whose workspace is a static

@@ -398,3 +398,50 @@ __global__ void k_ovf(const u32 *rp, const u32 *ci, u32 n, int pass, double *a, 
         }
     }
 }
+
+// ---- edge orbit counts (Lemma 4edgeorbit).  At every slot s = (u, v):
+// E_i<u,v> for i = 0..11, u the endpoint in the vertex orbit of larger
+// index (slot (v, u) holds the other orientation):
+//   E0 = d(u)-1                     E1 = T(u,v)
+//   E2 = sum_{x in N(u)\v} (d(x)-1) - T(u,v) = N1(u) - (d(v)-1) - T(u,v)
+//   E3 = (d(u)-1)(d(v)-1) - T(u,v)  E4 = C(d(u)-1, 2)     E5 = C4(u,v)
+//   E6 = T(u) - T(u,v)              E7 = sum over triangles (u,v,x) of d(x)-2
+//   E8 = T(u,v)(d(u)-2)             E9 = sum over triangles (u,v,x) of T(u,x)-1
+//   E10 = C(T(u,v), 2)              E11 = K4(u,v)
+// One wave per 64 slots; the 64 x 12 words go through LDS so that the rows
+// are written with contiguous stores.
+#define NEORB 12
+__global__ void __launch_bounds__(WAVE) k_edge_orbits(const u32 *src, const u32 *ci,
+                                                      const u32 *deg, const u32 *T,
+                                                      const u64 *Tv, const u64 *N1,
+                                                      const u64 *C4e, const u64 *E7,
+                                                      const u64 *E9, const u64 *K4e, u64 M2,
+                                                      u64 *E) {
+    __shared__ u64 tile[WAVE * NEORB];
+    const u32 lane = threadIdx.x;
+    for (u64 base = (u64)blockIdx.x * WAVE; base < M2; base += (u64)gridDim.x * WAVE) {
+        const u64 s = base + lane;
+        const u32 rows = M2 - base < WAVE ? (u32)(M2 - base) : WAVE;
+        if (s < M2) {
+            const u32 u = src[s], v = ci[s];
+            const u64 du = deg[u], dv = deg[v], t = T[s];
+            u64 *o = tile + (u64)lane * NEORB;
+            o[0] = du - 1;
+            o[1] = t;
+            o[2] = N1[u] - (dv - 1) - t;
+            o[3] = (du - 1) * (dv - 1) - t;
+            o[4] = c2((i64)du - 1);
+            o[5] = C4e[s];
+            o[6] = Tv[u] - t;
+            o[7] = E7[s];
+            o[8] = t * (du - 2);
+            o[9] = E9[s];
+            o[10] = c2((i64)t);
+            o[11] = K4e[s];
+        }
+        __syncthreads();
+        u64 *dst = E + base * NEORB;
+        for (u32 i = lane; i < rows * NEORB; i += WAVE) dst[i] = tile[i];
+        __syncthreads();
+    }
+}

@@ -492,7 +492,7 @@ int relabel_input(const u32 *rp, const u32 *ci, u32 n, u64 m, void *ws, const La
 }
 
 int count_impl(const u32 *rp, const u32 *ci, u32 n, u64 m, const u64 *vptr, u32 B, int k_max,
-               u64 *counts, unsigned char *ovf, void *ws,
+               u64 *counts, unsigned char *ovf, u64 *edge_out, void *ws,
                u64 ws_bytes, u64 *ws_required, hipStream_t s, const orb_opts *opts,
                bool query_only, Plan *pl = nullptr, u32 *nwg_fit = nullptr) {
     const bool cap = pl && pl->capture;
@@ -502,6 +502,7 @@ int count_impl(const u32 *rp, const u32 *ci, u32 n, u64 m, const u64 *vptr, u32 
     if (flags & ~(ORB_NONINDUCED | ORB_TIMING | ORB_RELABEL)) return ORB_E_INVALID_ARG;
     const bool relabel = (flags & ORB_RELABEL) != 0;
     if (relabel && (vptr || opts->features_out || opts->steps_out)) return ORB_E_INVALID_ARG;
+    if (edge_out && (relabel || vptr || k_max < 4)) return ORB_E_INVALID_ARG;
     const u32 sched = opts ? opts->schedule : ORB_SCHED_ID;
     if (sched > ORB_SCHED_MLP || (opts && opts->groups > ORB_GROUPS_WAVE))
         return ORB_E_INVALID_ARG;
@@ -694,6 +695,12 @@ int count_impl(const u32 *rp, const u32 *ci, u32 n, u64 m, const u64 *vptr, u32 
             HCHK(hipGetLastError());
         }
         tm.mark("trisweep");
+        if (edge_out) {
+            k_edge_orbits<<<grid_for(M2, WAVE), WAVE, 0, s>>>(src, ci, deg, T, Tv, N1, C4e, E7, E9,
+                                                            K4e, M2, edge_out);
+            HCHK(hipGetLastError());
+            tm.mark("edge_orbits");
+        }
     }
     if (k_max >= 5) {
         if (ntri) {
@@ -796,7 +803,17 @@ int orbit_count_ex(const uint32_t *row_ptr, const uint32_t *col_idx, uint32_t n,
                    uint64_t ws_bytes, uint64_t *ws_required, void *stream,
                    const orb_opts *opts) {
     return count_impl(row_ptr, col_idx, n, m, nullptr, 0, k_max, (u64 *)counts, overflow_flags,
-                      workspace, ws_bytes, (u64 *)ws_required, (hipStream_t)stream, opts, false);
+                      nullptr, workspace, ws_bytes, (u64 *)ws_required, (hipStream_t)stream, opts, false);
+}
+
+int orbit_count_edges(const uint32_t *row_ptr, const uint32_t *col_idx, uint32_t n, uint64_t m,
+                      int k_max, uint64_t *counts, uint64_t *edge_counts, void *workspace,
+                      uint64_t ws_bytes, uint64_t *ws_required, void *stream,
+                      const orb_opts *opts) {
+    if (!edge_counts || k_max < 4) return ORB_E_INVALID_ARG;
+    return count_impl(row_ptr, col_idx, n, m, nullptr, 0, k_max, (u64 *)counts, nullptr,
+                      (u64 *)edge_counts, workspace, ws_bytes, (u64 *)ws_required,
+                      (hipStream_t)stream, opts, false);
 }
 
 int orbit_count_noalloc(const uint32_t *row_ptr, const uint32_t *col_idx, uint32_t n,
@@ -812,14 +829,14 @@ int orbit_count_noalloc(const uint32_t *row_ptr, const uint32_t *col_idx, uint32
     // size the count for the static buffer (validates the graph on the way)
     u32 nwg = 0;
     u64 need = 0;
-    rc = count_impl(row_ptr, col_idx, n, m, nullptr, 0, k_max, (u64 *)counts, nullptr, ws,
+    rc = count_impl(row_ptr, col_idx, n, m, nullptr, 0, k_max, (u64 *)counts, nullptr, nullptr, ws,
                     ORB_NOALLOC_BYTES, &need, s, nullptr, true, nullptr, &nwg);
     if (rc) return rc;
     if (need > ORB_NOALLOC_BYTES) return ORB_E_TOO_LARGE;
     orb_opts o;
     memset(&o, 0, sizeof o);
     o.num_wg = nwg;
-    return count_impl(row_ptr, col_idx, n, m, nullptr, 0, k_max, (u64 *)counts, nullptr, ws,
+    return count_impl(row_ptr, col_idx, n, m, nullptr, 0, k_max, (u64 *)counts, nullptr, nullptr, ws,
                       ORB_NOALLOC_BYTES, nullptr, s, &o, false);
 }
 
@@ -835,7 +852,7 @@ int orbit_workspace_query(const uint32_t *row_ptr, const uint32_t *col_idx, uint
     void *tmp = nullptr;
     if (hipMalloc(&tmp, L.p1_end) != hipSuccess) return ORB_E_DEVICE;
     u64 req = 0;
-    int rc = count_impl(row_ptr, col_idx, n, m, nullptr, 0, k_max, nullptr, nullptr, tmp, L.p1_end, &req,
+    int rc = count_impl(row_ptr, col_idx, n, m, nullptr, 0, k_max, nullptr, nullptr, nullptr, tmp, L.p1_end, &req,
                         (hipStream_t)stream, opts, true);
     (void)hipFree(tmp);
     if (rc) return rc;
@@ -862,7 +879,7 @@ int orbit_count_batched(const uint64_t *vptr, uint32_t num_graphs, const uint32_
                         uint64_t *ws_required, void *stream, const orb_opts *opts) {
     if (!vptr) return ORB_E_INVALID_ARG;
     return count_impl(row_ptr, col_idx, n, m, (const u64 *)vptr, num_graphs, k_max,
-                      (u64 *)counts, nullptr, workspace, ws_bytes, (u64 *)ws_required,
+                      (u64 *)counts, nullptr, nullptr, workspace, ws_bytes, (u64 *)ws_required,
                       (hipStream_t)stream, opts, false);
 }
 
@@ -878,7 +895,7 @@ int orbit_workspace_query_batched(const uint64_t *vptr, uint32_t num_graphs,
     if (hipMalloc(&tmp, L.p1_end) != hipSuccess) return ORB_E_DEVICE;
     u64 req = 0;
     int rc = count_impl(row_ptr, col_idx, n, m, (const u64 *)vptr, num_graphs, k_max, nullptr,
-                        nullptr, tmp, L.p1_end, &req, (hipStream_t)stream, opts, true);
+                        nullptr, nullptr, tmp, L.p1_end, &req, (hipStream_t)stream, opts, true);
     (void)hipFree(tmp);
     if (rc) return rc;
     *bytes = req;
@@ -899,7 +916,7 @@ int orbit_autotune(const uint64_t *vptr, uint32_t num_graphs, const uint32_t *ro
     hipStream_t s = (hipStream_t)stream;
     auto run = [&](const orb_opts &x, float *ms) -> int {
         int rc = count_impl(row_ptr, col_idx, n, m, (const u64 *)vptr, num_graphs, k_max,
-                            (u64 *)counts, nullptr, workspace, ws_bytes, nullptr, s, &x, false);
+                            (u64 *)counts, nullptr, nullptr, workspace, ws_bytes, nullptr, s, &x, false);
         if (rc) return rc;
         float t = 0;
         for (int i = 0; i < g_nphase; i++) t += g_phase_ms[i];
@@ -958,7 +975,7 @@ int orbit_plan_create(const uint64_t *vptr, uint32_t num_graphs, const uint32_t 
     // 1. an ordinary run validates the input and fixes the sizes
     Plan pl;
     int rc = count_impl(row_ptr, col_idx, n, m, (const u64 *)vptr, num_graphs, k_max,
-                        (u64 *)counts, nullptr, workspace, ws_bytes, nullptr, s, &o, false, &pl);
+                        (u64 *)counts, nullptr, nullptr, workspace, ws_bytes, nullptr, s, &o, false, &pl);
     if (rc) return rc;
     if (n == 0) return ORB_E_INVALID_ARG;  // nothing to capture
     // 2. the same launches, captured on a private stream
@@ -970,7 +987,7 @@ int orbit_plan_create(const uint64_t *vptr, uint32_t num_graphs, const uint32_t 
     }
     pl.capture = true;
     rc = count_impl(row_ptr, col_idx, n, m, (const u64 *)vptr, num_graphs, k_max,
-                    (u64 *)counts, nullptr, workspace, ws_bytes, nullptr, cs, &o, false, &pl);
+                    (u64 *)counts, nullptr, nullptr, workspace, ws_bytes, nullptr, cs, &o, false, &pl);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(cs, &g);
     (void)hipStreamDestroy(cs);

@@ -28,7 +28,7 @@ EXPORTS = ("orbit_num_orbits", "orbit_count", "orbit_workspace_query", "orbit_co
            "orbit_mlp_predict", "orbit_mlp_grad", "orbit_mlp_train", "orbit_count_batched",
            "orbit_workspace_query_batched", "orbit_autotune", "orbit_plan_create",
            "orbit_plan_launch", "orbit_plan_status", "orbit_plan_destroy",
-           "orbit_count_noalloc", "orbit_noalloc_capacity")
+           "orbit_count_noalloc", "orbit_noalloc_capacity", "orbit_count_edges")
 
 
 class OrbError(RuntimeError):
@@ -95,6 +95,9 @@ def _load(path=LIB):
         f.restype = ctypes.c_int
     lib.orbit_plan_destroy.argtypes = [vp]
     lib.orbit_plan_destroy.restype = ctypes.c_int
+    lib.orbit_count_edges.argtypes = [vp, vp, u32, u64, ctypes.c_int, vp, vp, vp, u64,
+                                      ctypes.POINTER(u64), vp, ctypes.POINTER(_Opts)]
+    lib.orbit_count_edges.restype = ctypes.c_int
     lib.orbit_count_noalloc.argtypes = [vp, vp, u32, u64, ctypes.c_int, vp, vp]
     lib.orbit_count_noalloc.restype = ctypes.c_int
     lib.orbit_noalloc_capacity.argtypes = []
@@ -234,6 +237,24 @@ def count(row_ptr, col_idx, k_max=5, noninduced=False, num_wg=0, groups="auto",
     optional uint8 device tensor [n] for the overflow flags."""
     c = Counter(row_ptr, col_idx, k_max, noninduced, num_wg, groups=groups, relabel=relabel)
     return c.run(overflow_flags=overflow_flags).clone()
+
+
+def count_edges(row_ptr, col_idx, k_max=4, noninduced=False, groups="auto"):
+    """(vertex counts [n, K], edge orbit counts [2m, 12]) as torch tensors
+    (int64 holding uint64 bits): orbit_count_edges.  Row s of the edge
+    counts is E_0..E_11 of CSR slot s = (u, v), oriented with u in the
+    endpoint vertex orbit of larger index."""
+    import torch
+    c = Counter(row_ptr, col_idx, k_max, noninduced, groups=groups)
+    m2 = 2 * c.m
+    edges = torch.empty((max(m2, 1), 12), dtype=torch.int64, device=c.rp.device)
+    need = ctypes.c_uint64(0)
+    _check(_lib.orbit_count_edges(ctypes.c_void_p(c.rp.data_ptr()), ctypes.c_void_p(c.ci.data_ptr()),
+                                  c.n, c.m, k_max, ctypes.c_void_p(c.out.data_ptr()),
+                                  ctypes.c_void_p(edges.data_ptr()), ctypes.c_void_p(c.ws.data_ptr()),
+                                  c.ws_bytes, ctypes.byref(need), _stream_ptr(None),
+                                  ctypes.byref(c.opts)), "orbit_count_edges")
+    return c.out[:c.n].clone(), edges[:m2]
 
 
 def to_u64(t) -> np.ndarray:
