@@ -145,6 +145,29 @@ int orbit_count_edges(const uint32_t *row_ptr, const uint32_t *col_idx, uint32_t
                       uint64_t ws_bytes, uint64_t *ws_required, void *stream,
                       const orb_opts *opts);
 
+/* Number of patterns with 2..k_max vertices (3, 9 or 30); 0 if k_max is
+ * invalid. */
+int orbit_num_patterns(int k_max);
+
+/* Global counts and VOC distributions of a count array (the paper's
+ * experiments section, "VOC distributions", Figs. orb70CCD, orb17CCD and
+ * H9CCD), asynchronous on `stream`.  counts: DEVICE, n x K uint64 as written
+ * by the count calls (K = orbit_num_orbits(k_max)).  Outputs, DEVICE,
+ * overwritten:
+ *   orbit_sums[2o], [2o+1]: low and high 64 bits of sum_u counts[u][o];
+ *   pattern_counts (nullable, 2 x orbit_num_patterns(k_max)): the number of
+ *     induced copies of pattern H_h (low, high words): the sum of one of its
+ *     orbits divided by the number of its vertices in that orbit;
+ *   hist[o * 65 + b]: vertices whose count of orbit o has bit length b
+ *     (b = 0: count 0; else 2^(b-1) <= count < 2^b), so the fraction of
+ *     vertices with count >= 2^(b-1) -- the complementary cumulative
+ *     distribution the paper plots -- is sum_{b' >= b} hist[o*65+b'] / n.
+ * Sums are exact when every row is (counts modulo 2^64 otherwise; see the
+ * overflow flags of orbit_count_ex).  For induced counts the sum over an
+ * orbit of H_h is the same multiple of its size for every orbit of H_h. */
+int orbit_voc_summary(const uint64_t *counts, uint32_t n, int k_max, uint64_t *orbit_sums,
+                      uint64_t *pattern_counts, uint64_t *hist, void *stream);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the count
  * of orbit_count_ex with default options, whose workspace is a static

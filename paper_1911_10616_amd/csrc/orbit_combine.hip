@@ -445,3 +445,76 @@ __global__ void __launch_bounds__(WAVE) k_edge_orbits(const u32 *src, const u32 
         __syncthreads();
     }
 }
+
+// ---- VOC distributions and global pattern counts (the paper's
+// experiments section, "VOC distributions"; Figs. orb70CCD, orb17CCD,
+// H9CCD).  Per orbit o of the K columns:
+//   sums[2o], sums[2o+1]: low and high 64 bits of sum_u counts[u][o];
+//   hist[o * 65 + b]: number of vertices whose count has bit length b
+//     (b = 0 for a zero count, else 2^(b-1) <= count < 2^b), so that the
+//     complementary cumulative distribution -- the fraction of vertices
+//     with count >= x -- is exact at x = 2^(b-1): sum_{b' >= b} hist / n.
+// Elements are read row by row (coalesced); each workgroup keeps its
+// histogram and sums in LDS and flushes them once.  A 64-bit add returns
+// the old value, so its carry into the high word is known exactly.
+#define VOC_BINS 65
+__device__ inline void add_u128(u64 *lo, u64 *hi, u64 v) {
+    if (!v) return;
+    const u64 old = atomicAdd(lo, v);
+    if (old + v < old) atomicAdd(hi, 1ull);
+}
+__global__ void __launch_bounds__(WG) k_voc(const u64 *counts, u32 n, int K, u64 *sums,
+                                           u64 *hist) {
+    __shared__ u32 lh[ORB_NORB * VOC_BINS];
+    __shared__ u64 ls[ORB_NORB * 2];
+    for (u32 i = threadIdx.x; i < (u32)K * VOC_BINS; i += WG) lh[i] = 0;
+    for (u32 i = threadIdx.x; i < (u32)K * 2; i += WG) ls[i] = 0;
+    __syncthreads();
+    const u64 total = (u64)n * K;
+    for (u64 i = GTID; i < total; i += GSTRIDE) {
+        const u32 o = (u32)(i % K);
+        const u64 c = counts[i];
+        const u32 b = c ? 64 - __clzll((long long)c) : 0;
+        atomicAdd(&lh[o * VOC_BINS + b], 1u);
+        add_u128(&ls[2 * o], &ls[2 * o + 1], c);
+    }
+    __syncthreads();
+    for (u32 i = threadIdx.x; i < (u32)K * VOC_BINS; i += WG)
+        if (lh[i]) atomicAdd(&hist[i], (u64)lh[i]);
+    for (u32 o = threadIdx.x; o < (u32)K; o += WG) {
+        add_u128(&sums[2 * o], &sums[2 * o + 1], ls[2 * o]);
+        if (ls[2 * o + 1]) atomicAdd(&sums[2 * o + 1], ls[2 * o + 1]);
+    }
+}
+
+// 128-bit value (hi, lo) divided by a small d, by 32-bit limbs
+__device__ inline void div_u128_small(u64 hi, u64 lo, u32 d, u64 *qhi, u64 *qlo) {
+    const u32 limb[4] = {(u32)(hi >> 32), (u32)hi, (u32)(lo >> 32), (u32)lo};
+    u32 q[4];
+    u64 r = 0;
+    for (int i = 0; i < 4; i++) {
+        const u64 x = (r << 32) | limb[i];
+        q[i] = (u32)(x / d);
+        r = x % d;
+    }
+    *qhi = ((u64)q[0] << 32) | q[1];
+    *qlo = ((u64)q[2] << 32) | q[3];
+}
+
+// Copies of each pattern: the sum over vertices of one of its orbits
+// divided by the number of pattern vertices in that orbit (every induced
+// copy puts that many vertices in the orbit); the first orbit of each
+// pattern is used.  pats[2h], pats[2h+1] = low, high 64 bits.
+__global__ void k_voc_patterns(const u64 *sums, int K, u64 *pats) {
+    if (GTID != 0) return;
+    int last = -1;
+    for (int o = 0; o < K; o++) {
+        const int h = ORB_ORBIT_PATTERN[o];
+        if (h == last) continue;
+        last = h;
+        u64 qh, ql;
+        div_u128_small(sums[2 * o + 1], sums[2 * o], ORB_ORBIT_SIZE[o], &qh, &ql);
+        pats[2 * h] = ql;
+        pats[2 * h + 1] = qh;
+    }
+}

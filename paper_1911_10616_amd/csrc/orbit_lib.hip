@@ -816,6 +816,35 @@ int orbit_count_edges(const uint32_t *row_ptr, const uint32_t *col_idx, uint32_t
                       (hipStream_t)stream, opts, false);
 }
 
+int orbit_num_patterns(int k_max) {
+    switch (k_max) {
+        case 3: return 3;
+        case 4: return 9;
+        case 5: return ORB_NPATTERN;
+        default: return 0;
+    }
+}
+
+int orbit_voc_summary(const uint64_t *counts, uint32_t n, int k_max, uint64_t *orbit_sums,
+                      uint64_t *pattern_counts, uint64_t *hist, void *stream) {
+    const int K = orbit_num_orbits(k_max);
+    if (!K || !orbit_sums || !hist || (n && !counts)) return ORB_E_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    int rc = zero_u64(orbit_sums, 2ull * K, s);
+    if (!rc) rc = zero_u64(hist, (u64)K * VOC_BINS, s);
+    if (rc) return rc;
+    if (n) {
+        k_voc<<<grid_for((u64)n * K, WG), WG, 0, s>>>((const u64 *)counts, n, K,
+                                                     (u64 *)orbit_sums, (u64 *)hist);
+        HCHK(hipGetLastError());
+    }
+    if (pattern_counts) {
+        k_voc_patterns<<<1, 64, 0, s>>>((const u64 *)orbit_sums, K, (u64 *)pattern_counts);
+        HCHK(hipGetLastError());
+    }
+    return ORB_OK;
+}
+
 int orbit_count_noalloc(const uint32_t *row_ptr, const uint32_t *col_idx, uint32_t n,
                         uint64_t m, int k_max, uint64_t *counts, void *stream) {
     if (!orbit_num_orbits(k_max) || 2 * m >= (1ull << 32)) return ORB_E_INVALID_ARG;

@@ -139,9 +139,21 @@ def inverse(A):
     return inv
 
 
+def orbit_tables():
+    """(pattern of each orbit, number of pattern vertices in each orbit)."""
+    pat = [0] * NORB
+    size = [0] * NORB
+    for h, (k, es, orbit) in enumerate(patterns()):
+        for o in orbit:
+            pat[o] = h
+            size[o] += 1
+    return pat, size
+
+
 def header_text():
     A = transform()
     inv = inverse(A)
+    opat, osize = orbit_tables()
     rows = []
     ptr = [0]
     for i in range(NORB):
@@ -161,6 +173,11 @@ def header_text():
         "static const uint16_t ORB_AINV_PTR[74] = {" + ", ".join(map(str, ptr)) + "};",
         "static const uint8_t ORB_AINV_COL[ORB_AINV_NNZ] = {" + ", ".join(str(c) for c, _ in rows) + "};",
         "static const int16_t ORB_AINV_VAL[ORB_AINV_NNZ] = {" + ", ".join(str(v) for _, v in rows) + "};",
+        "/* Pattern H_h of each orbit and the number of its vertices in the orbit",
+        " * (Fig. node_orbits, orbits of unlabelled vertices by automorphisms). */",
+        "#define ORB_NPATTERN 30",
+        "static const uint8_t ORB_ORBIT_PATTERN[73] = {" + ", ".join(map(str, opat)) + "};",
+        "static const uint8_t ORB_ORBIT_SIZE[73] = {" + ", ".join(map(str, osize)) + "};",
         "",
     ]
     return "\n".join(lines)

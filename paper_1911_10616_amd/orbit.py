@@ -28,7 +28,8 @@ EXPORTS = ("orbit_num_orbits", "orbit_count", "orbit_workspace_query", "orbit_co
            "orbit_mlp_predict", "orbit_mlp_grad", "orbit_mlp_train", "orbit_count_batched",
            "orbit_workspace_query_batched", "orbit_autotune", "orbit_plan_create",
            "orbit_plan_launch", "orbit_plan_status", "orbit_plan_destroy",
-           "orbit_count_noalloc", "orbit_noalloc_capacity", "orbit_count_edges")
+           "orbit_count_noalloc", "orbit_noalloc_capacity", "orbit_count_edges",
+           "orbit_num_patterns", "orbit_voc_summary")
 
 
 class OrbError(RuntimeError):
@@ -98,6 +99,10 @@ def _load(path=LIB):
     lib.orbit_count_edges.argtypes = [vp, vp, u32, u64, ctypes.c_int, vp, vp, vp, u64,
                                       ctypes.POINTER(u64), vp, ctypes.POINTER(_Opts)]
     lib.orbit_count_edges.restype = ctypes.c_int
+    lib.orbit_num_patterns.argtypes = [ctypes.c_int]
+    lib.orbit_num_patterns.restype = ctypes.c_int
+    lib.orbit_voc_summary.argtypes = [vp, u32, ctypes.c_int, vp, vp, vp, vp]
+    lib.orbit_voc_summary.restype = ctypes.c_int
     lib.orbit_count_noalloc.argtypes = [vp, vp, u32, u64, ctypes.c_int, vp, vp]
     lib.orbit_count_noalloc.restype = ctypes.c_int
     lib.orbit_noalloc_capacity.argtypes = []
@@ -255,6 +260,39 @@ def count_edges(row_ptr, col_idx, k_max=4, noninduced=False, groups="auto"):
                                   c.ws_bytes, ctypes.byref(need), _stream_ptr(None),
                                   ctypes.byref(c.opts)), "orbit_count_edges")
     return c.out[:c.n].clone(), edges[:m2]
+
+
+VOC_BINS = 65
+
+
+def voc_summary(counts, k_max=5, stream=None):
+    """orbit_voc_summary of a count tensor [n, K] on the GPU.  Returns
+    (orbit_sums, pattern_counts, hist): Python ints per orbit and per
+    pattern (the 128-bit words joined), and a numpy [K, 65] histogram of the
+    counts by bit length."""
+    import torch
+    n = counts.shape[0]
+    K = num_orbits(k_max)
+    P = _lib.orbit_num_patterns(k_max)
+    sums = torch.empty(2 * K, dtype=torch.int64, device=counts.device)
+    pats = torch.empty(2 * P, dtype=torch.int64, device=counts.device)
+    hist = torch.empty((K, VOC_BINS), dtype=torch.int64, device=counts.device)
+    _check(_lib.orbit_voc_summary(ctypes.c_void_p(counts.data_ptr()), n, k_max,
+                                  ctypes.c_void_p(sums.data_ptr()), ctypes.c_void_p(pats.data_ptr()),
+                                  ctypes.c_void_p(hist.data_ptr()), _stream_ptr(stream)),
+           "orbit_voc_summary")
+    s = to_u64(sums).reshape(K, 2)
+    p = to_u64(pats).reshape(P, 2)
+    join = lambda w: [int(a) | (int(b) << 64) for a, b in w]
+    return join(s), join(p), to_u64(hist)
+
+
+def ccd(hist_row, n):
+    """Complementary cumulative distribution of one orbit from its
+    bit-length histogram: [(x, fraction of vertices with count >= x)] for
+    x = 1, 2, 4, ... (the points where the histogram makes it exact)."""
+    tail = np.cumsum(np.asarray(hist_row, np.float64)[::-1])[::-1]
+    return [(1 << (b - 1), float(tail[b]) / max(n, 1)) for b in range(1, VOC_BINS) if tail[b] > 0]
 
 
 def to_u64(t) -> np.ndarray:

@@ -58,3 +58,13 @@ def test_product_does_not_use_the_oracle():
                 txt = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in txt and "from oracle" not in txt, f
                 assert "orbit_oracle" not in txt, f
+
+
+def test_orbit_tables_match_oracle():
+    """The product's orbit -> pattern and orbit-size tables (its own
+    transcription) agree with the oracle's."""
+    from paper_1911_10616_amd import gen_tables
+    pat, size = gen_tables.orbit_tables()
+    t = oracle.tables()
+    assert list(pat) == [int(x) for x in t["orbit_graphlet"]]
+    assert list(size) == [int(x) for x in t["orbit_size"]]
