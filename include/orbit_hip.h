@@ -78,6 +78,11 @@ extern "C" {
                                degree); the counts come back under the caller's ids.  One
                                graph only (not batched), not with features_out/steps_out;
                                the workspace grows by about 8m + 40n bytes. */
+#define ORB_SERIAL_GROUPS 0x8u /* k_max = 5: run the three independent orbit groups
+                               (pair sweep, 5-cycles, second clique pass) one after
+                               another on `stream` instead of overlapping them on two
+                               helper streams (section "Runtime distribution and
+                               parallel speedup" runs these groups in parallel) */
 
 /* order in which the per-source kernels take their sources (the counts
  * are the same under every schedule; only the work balance changes) */
@@ -274,6 +279,12 @@ int orbit_plan_destroy(orb_plan *plan);
 
 /* Human-readable text of a status code (static storage). */
 const char *orbit_strerror(int status);
+
+/* GPU times (ms) of the kernels of the three 5-vertex orbit groups in the
+ * calling thread's last call with ORB_TIMING ("pairs", "c5",
+ * "clique2_k4terms"), each from events on the stream it ran on (they may
+ * overlap): writes up to max_kernels values and names and returns how many. */
+int orbit_last_kernel_times(float *ms, const char **names, int max_kernels);
 
 /* Per-phase GPU times (ms) of the calling thread's last orbit_count_ex with
  * ORB_TIMING: writes up to max_phases values and their names (static

@@ -47,8 +47,12 @@ struct Layout {
     // phase 2
     Buf tri_c, tri_sab, tri_sac, tri_sbc, T, Tin, Tmid, tllen, tlptr, tlcur, tl, E7, E9, C4e,
         K4e, Q, K4t, Tv, N1, C4v, K4v, ni, vacc, cacc, feat, pred, sbin, shist, order, scratch;
+    // k_max = 5: scratch of the 5-cycle kernel and of the second clique pass,
+    // apart from the pair sweep's so that the three orbit groups can overlap
+    Buf scratch_c5, scratch_clq;
     u64 total = 0;
-    u64 stride = 0;
+    u64 stride = 0, stride_c5 = 0, stride_clq = 0;
+    u32 nwg_c5 = 0;
     u32 nwg = 0;
     u32 per_wg = 1;  // execution groups (each with its own scratch) per workgroup
 };
@@ -106,6 +110,10 @@ void layout_phase1(Layout &L, u32 n, u64 m, bool relabel = false) {
 u64 pair_stride(u32 n, bool wave_maps) {
     return 3 * align_up(8ull * n, 256) + align_up(4ull * n, 256) +
            (wave_maps ? 2 * align_up(4ull * WAVES_PER_WG * n, 256) : 0) + 256;
+}
+// 5-cycles: Wm (u32), P, CI (u64), touched (u32), mark (u8)
+u64 c5_stride(u32 n) {
+    return 2 * align_up(4ull * n, 256) + 2 * align_up(8ull * n, 256) + align_up(n, 256) + 256;
 }
 u64 clique_stride(u32 dmax) {
     u64 W = (dmax + 63) / 64;
@@ -166,6 +174,15 @@ void layout_phase2(Layout &L, u32 n, u32 mapn, u64 m, u64 ntri, u32 dmax, int k_
     u64 sbytes = (u64)nwg * per_wg * stride;
     if (sbytes < 48ull * n + 256) sbytes = 48ull * n + 256;
     place(c, L.scratch, sbytes);
+    if (k_max >= 5) {
+        // the 5-cycle kernel runs at most 256 workgroups when its maps are
+        // large (measured faster on big graphs)
+        L.nwg_c5 = (mapn > 65536 && nwg > 256) ? 256 : nwg;
+        L.stride_c5 = align_up(c5_stride(mapn), 256);
+        L.stride_clq = align_up(cs, 256);
+        place(c, L.scratch_c5, (u64)L.nwg_c5 * per_wg * L.stride_c5);
+        place(c, L.scratch_clq, (u64)nwg * per_wg * L.stride_clq);
+    }
     L.total = align_up(c, 256);
 }
 
@@ -225,12 +242,12 @@ int zero_ranges(int which, u32 n, bool wave_maps, ZeroRange *r) {
     return 2;
 }
 
-int zero_scratch(int which, u32 mapn, unsigned char *scratch, const Layout &L, u32 nwg,
-                 hipStream_t s) {
+int zero_scratch(int which, u32 mapn, unsigned char *scratch, u64 stride, const Layout &L,
+                 u32 nwg, hipStream_t s) {
     ZeroRange r[2];
     int k = zero_ranges(which, mapn, L.per_wg > 1, r);
     for (int i = 0; i < k; i++)
-        k_zero_rows<<<grid_for(r[i].len / 8 * nwg, WG), WG, 0, s>>>(scratch + r[i].off, L.stride,
+        k_zero_rows<<<grid_for(r[i].len / 8 * nwg, WG), WG, 0, s>>>(scratch + r[i].off, stride,
                                                                    r[i].len / 8, nwg);
     HCHK(hipGetLastError());
     return ORB_OK;
@@ -263,16 +280,35 @@ int group_size(u32 n, u64 m) {
         }                                                       \
     } while (0)
 
+// Kernels timed on their own streams (they may overlap): the pair sweep,
+// the 5-cycles, the second clique pass with its triangle terms.
+const int kTimedKernels = 3;
+const char *const kTimedKernelName[kTimedKernels] = {"pairs", "c5", "clique2_k4terms"};
+thread_local float g_kernel_ms[kTimedKernels];
+thread_local int g_kernel_used = 0;
+
 struct Timer {
     bool on;
     hipStream_t st;
     hipEvent_t ev[kMaxPhases + 1];
+    hipEvent_t kev[2 * kTimedKernels];
     const char *names[kMaxPhases];
     int k = 0;
+    int kused = 0;
     Timer(bool on_, hipStream_t s) : on(on_), st(s) {
-        if (on)
+        if (on) {
             for (int i = 0; i <= kMaxPhases; i++) (void)hipEventCreate(&ev[i]);
-        if (on) (void)hipEventRecord(ev[0], st);
+            for (int i = 0; i < 2 * kTimedKernels; i++) (void)hipEventCreate(&kev[i]);
+            (void)hipEventRecord(ev[0], st);
+        }
+    }
+    void kbegin(int i, hipStream_t s) {
+        if (on) (void)hipEventRecord(kev[2 * i], s);
+    }
+    void kend(int i, hipStream_t s) {
+        if (!on) return;
+        (void)hipEventRecord(kev[2 * i + 1], s);
+        kused |= 1 << i;
     }
     void mark(const char *name) {
         if (!on || k >= kMaxPhases) return;
@@ -283,6 +319,15 @@ struct Timer {
     void finish() {
         if (!on) return;
         (void)hipEventSynchronize(ev[k]);
+        g_kernel_used = kused;
+        for (int i = 0; i < kTimedKernels; i++) {
+            float ms = 0;
+            if (kused >> i & 1) {
+                (void)hipEventSynchronize(kev[2 * i + 1]);
+                (void)hipEventElapsedTime(&ms, kev[2 * i], kev[2 * i + 1]);
+            }
+            g_kernel_ms[i] = ms;
+        }
         g_nphase = k;
         for (int i = 0; i < k; i++) {
             float ms = 0;
@@ -292,8 +337,9 @@ struct Timer {
         }
     }
     ~Timer() {
-        if (on)
-            for (int i = 0; i <= kMaxPhases; i++) (void)hipEventDestroy(ev[i]);
+        if (!on) return;
+        for (int i = 0; i <= kMaxPhases; i++) (void)hipEventDestroy(ev[i]);
+        for (int i = 0; i < 2 * kTimedKernels; i++) (void)hipEventDestroy(kev[i]);
     }
 };
 
@@ -324,6 +370,32 @@ struct Plan {
     u64 ntri = 0;
     u32 maxlevel = 0, gmax = 0;
 };
+
+// Helper streams (default priority) and events of the overlapping orbit
+// groups, one set per thread and device, created on first use and kept: a
+// plan captured on this thread records them as branches of its graph.
+struct GroupStreams {
+    hipStream_t sb = nullptr, sc = nullptr;
+    hipEvent_t fork = nullptr, jb = nullptr, jc = nullptr;
+};
+const int kMaxGroupDevices = 64;
+thread_local GroupStreams g_group_streams[kMaxGroupDevices];
+
+int group_streams(GroupStreams **out) {
+    int dev = -1;
+    HCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxGroupDevices) return ORB_E_DEVICE;
+    GroupStreams &g = g_group_streams[dev];
+    if (!g.sb) {
+        HCHK(hipStreamCreateWithFlags(&g.sb, hipStreamNonBlocking));
+        HCHK(hipStreamCreateWithFlags(&g.sc, hipStreamNonBlocking));
+        HCHK(hipEventCreateWithFlags(&g.fork, hipEventDisableTiming));
+        HCHK(hipEventCreateWithFlags(&g.jb, hipEventDisableTiming));
+        HCHK(hipEventCreateWithFlags(&g.jc, hipEventDisableTiming));
+    }
+    *out = &g;
+    return ORB_OK;
+}
 
 // zero n64 u64 words at p (a kernel, capturable)
 int zero_u64(void *p, u64 n64, hipStream_t s) {
@@ -499,7 +571,8 @@ int count_impl(const u32 *rp, const u32 *ci, u32 n, u64 m, const u64 *vptr, u32 
     const u32 flags = opts ? opts->flags : 0u;
     const int K = orbit_num_orbits(k_max);
     if (!K) return ORB_E_INVALID_ARG;
-    if (flags & ~(ORB_NONINDUCED | ORB_TIMING | ORB_RELABEL)) return ORB_E_INVALID_ARG;
+    if (flags & ~(ORB_NONINDUCED | ORB_TIMING | ORB_RELABEL | ORB_SERIAL_GROUPS))
+        return ORB_E_INVALID_ARG;
     const bool relabel = (flags & ORB_RELABEL) != 0;
     if (relabel && (vptr || opts->features_out || opts->steps_out)) return ORB_E_INVALID_ARG;
     if (edge_out && (relabel || vptr || k_max < 4)) return ORB_E_INVALID_ARG;
@@ -589,7 +662,7 @@ int count_impl(const u32 *rp, const u32 *ci, u32 n, u64 m, const u64 *vptr, u32 
     const size_t clq_lds = 8ull * L.per_wg * clique_lds_words(clq_d);
     const u32 pair_kl = ((mapn < PAIR_KMAP_LDS ? mapn : PAIR_KMAP_LDS) + 1) & ~1u;
     const size_t pair_lds = (size_t)WAVES_PER_WG * pair_kl * 6;
-    const u32 c5_wg = (mapn > 65536 && L.nwg > 256) ? 256 : L.nwg;
+    const u32 c5_wg = L.nwg_c5;
     const u32 grp = L.nwg * L.per_wg, grp5 = c5_wg * L.per_wg;  // scratch rows in use
 
     // zero the accumulators (the contiguous phase-2 region up to ni) and
@@ -674,7 +747,7 @@ int count_impl(const u32 *rp, const u32 *ci, u32 n, u64 m, const u64 *vptr, u32 
     u32 *work = st->work;
     int wi = 0;
     if (k_max >= 4) {
-        rc = zero_scratch(0, mapn, scratch, L, grp, s);
+        rc = zero_scratch(0, mapn, scratch, L.stride, L, grp, s);
         if (rc) return rc;
         tm.mark("zero_c4");
         WITH_GP(wave_groups, k_c4<GPT><<<L.nwg, WG, 0, s>>>(rp, ci, rev, key, n, scratch, L.stride, work + wi++, order,
@@ -703,30 +776,64 @@ int count_impl(const u32 *rp, const u32 *ci, u32 n, u64 m, const u64 *vptr, u32 
         }
     }
     if (k_max >= 5) {
+        // From here the three orbit groups of the 5-vertex patterns read only
+        // finished data and write disjoint accumulators: the pair sweep
+        // (wedges and diamonds), the 5-cycles, and the second clique pass with
+        // its triangle terms.  Each has its own scratch; unless
+        // ORB_SERIAL_GROUPS, the last two run on helper streams forked from
+        // and joined back into `s` by events, so the three overlap on the GPU.
+        const bool conc = !(flags & ORB_SERIAL_GROUPS);
+        hipStream_t sb = s, sc = s;
+        GroupStreams *gs = nullptr;
+        unsigned char *scr_c5 = at<unsigned char>(ws, L.scratch_c5);
+        unsigned char *scr_clq = at<unsigned char>(ws, L.scratch_clq);
+        if (conc) {
+            rc = group_streams(&gs);
+            if (rc) return rc;
+            sb = gs->sb;
+            sc = gs->sc;
+            HCHK(hipEventRecord(gs->fork, s));
+            HCHK(hipStreamWaitEvent(sb, gs->fork, 0));
+            HCHK(hipStreamWaitEvent(sc, gs->fork, 0));
+        }
+        tm.kbegin(2, sc);
         if (ntri) {
-            WITH_GP(wave_groups, k_clique<GPT><<<L.nwg, WG, clq_lds, s>>>(2, n, rev, outptr, outnbr, outslot, triptr, tri_c,
-                                          tri_sbc, scratch, L.stride, dmax, clq_d, work + wi++, order, K4t, K4v, K4e,
+            WITH_GP(wave_groups, k_clique<GPT><<<L.nwg, WG, clq_lds, sc>>>(2, n, rev, outptr, outnbr, outslot, triptr, tri_c,
+                                          tri_sbc, scr_clq, L.stride_clq, dmax, clq_d, work + wi++, order, K4t, K4v, K4e,
                                           ni, st));
-            k_tri_k4terms<<<grid_for(ntri, WG), WG, 0, s>>>(src, ci, T, ntri, tri_c, tri_sab,
-                                                            tri_sac, tri_sbc, K4t, ni);
+            k_tri_k4terms<<<grid_for(ntri, WG), WG, 0, sc>>>(src, ci, T, ntri, tri_c, tri_sab,
+                                                             tri_sac, tri_sbc, K4t, ni);
             HCHK(hipGetLastError());
         }
-        tm.mark("clique2_k4terms");
-        rc = zero_scratch(1, mapn, scratch, L, grp, s);
+        tm.kend(2, sc);
+        if (!conc) tm.mark("clique2_k4terms");
+        rc = zero_scratch(1, mapn, scratch, L.stride, L, grp, s);
         if (rc) return rc;
-        tm.mark("zero_pairs");
+        if (!conc) tm.mark("zero_pairs");
+        tm.kbegin(0, s);
         WITH_GP(wave_groups, k_pairs<GPT><<<L.nwg, WG, pair_lds, s>>>(rp, ci, src, rev, deg, T, tlptr, tl, n, scratch, L.stride,
                                      work + wi++, order, mapn, gbase, pair_kl, steps_out,
                                      opts ? (u64 *)opts->pass_cycles_out : nullptr, Q, vacc, st));
         HCHK(hipGetLastError());
-        tm.mark("pairs");
-        rc = zero_scratch(2, mapn, scratch, L, grp5, s);
+        tm.kend(0, s);
+        if (!conc) tm.mark("pairs");
+        rc = zero_scratch(2, mapn, scr_c5, L.stride_c5, L, grp5, sb);
         if (rc) return rc;
-        tm.mark("zero_c5");
-        WITH_GP(wave_groups, k_c5<GPT><<<c5_wg, WG, 0, s>>>(rp, ci, key, outptr, outnbr, Tin, Tmid, n, scratch,
-                                  L.stride, work + wi++, order, mapn, gbase, steps_out, cacc, st));
+        if (!conc) tm.mark("zero_c5");
+        tm.kbegin(1, sb);
+        WITH_GP(wave_groups, k_c5<GPT><<<c5_wg, WG, 0, sb>>>(rp, ci, key, outptr, outnbr, Tin, Tmid, n, scr_c5,
+                                  L.stride_c5, work + wi++, order, mapn, gbase, steps_out, cacc, st));
         HCHK(hipGetLastError());
-        tm.mark("c5");
+        tm.kend(1, sb);
+        if (conc) {
+            HCHK(hipEventRecord(gs->jb, sb));
+            HCHK(hipEventRecord(gs->jc, sc));
+            HCHK(hipStreamWaitEvent(s, gs->jb, 0));
+            HCHK(hipStreamWaitEvent(s, gs->jc, 0));
+            tm.mark("groups");
+        } else {
+            tm.mark("c5");
+        }
     }
     WITH_GROUP(gsz, k_vert1<GG><<<grid_for((u64)n * GG, WG), WG, 0, s>>>(
                         rp, ci, rev, deg, T, Tv, N1, C4v, K4v, C4e, K4e, E9, Q, vacc, cacc, n, ni));
@@ -865,6 +972,7 @@ int orbit_count_noalloc(const uint32_t *row_ptr, const uint32_t *col_idx, uint32
     orb_opts o;
     memset(&o, 0, sizeof o);
     o.num_wg = nwg;
+    o.flags = ORB_SERIAL_GROUPS;  // one stream: no helper streams are created
     return count_impl(row_ptr, col_idx, n, m, nullptr, 0, k_max, (u64 *)counts, nullptr, nullptr, ws,
                       ORB_NOALLOC_BYTES, nullptr, s, &o, false);
 }
@@ -1133,6 +1241,17 @@ const char *orbit_strerror(int status) {
 int orbit_last_stats(uint64_t *vals, int max_vals) {
     int k = max_vals < 6 ? max_vals : 6;
     for (int i = 0; i < k; i++) vals[i] = g_stats[i];
+    return k;
+}
+
+int orbit_last_kernel_times(float *ms, const char **names, int max_kernels) {
+    int k = 0;
+    for (int i = 0; i < kTimedKernels && k < max_kernels; i++) {
+        if (!(g_kernel_used >> i & 1)) continue;
+        if (ms) ms[k] = g_kernel_ms[i];
+        if (names) names[k] = kTimedKernelName[i];
+        k++;
+    }
     return k;
 }
 

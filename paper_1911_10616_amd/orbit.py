@@ -18,6 +18,7 @@ NORB = 73
 ORB_NONINDUCED = 0x1
 ORB_TIMING = 0x2
 ORB_RELABEL = 0x4
+ORB_SERIAL_GROUPS = 0x8
 SCHED_ID, SCHED_STATIC, SCHED_MLP = 0, 1, 2
 SCHEDULES = {"id": SCHED_ID, "static": SCHED_STATIC, "mlp": SCHED_MLP}
 GROUPS = {"auto": 0, "wg": 1, "wave": 2}
@@ -29,7 +30,7 @@ EXPORTS = ("orbit_num_orbits", "orbit_count", "orbit_workspace_query", "orbit_co
            "orbit_workspace_query_batched", "orbit_autotune", "orbit_plan_create",
            "orbit_plan_launch", "orbit_plan_status", "orbit_plan_destroy",
            "orbit_count_noalloc", "orbit_noalloc_capacity", "orbit_count_edges",
-           "orbit_num_patterns", "orbit_voc_summary")
+           "orbit_num_patterns", "orbit_voc_summary", "orbit_last_kernel_times")
 
 
 class OrbError(RuntimeError):
@@ -66,6 +67,9 @@ def _load(path=LIB):
     lib.orbit_last_phase_times.argtypes = [ctypes.POINTER(ctypes.c_float),
                                            ctypes.POINTER(ctypes.c_char_p), ctypes.c_int]
     lib.orbit_last_phase_times.restype = ctypes.c_int
+    lib.orbit_last_kernel_times.argtypes = [ctypes.POINTER(ctypes.c_float),
+                                            ctypes.POINTER(ctypes.c_char_p), ctypes.c_int]
+    lib.orbit_last_kernel_times.restype = ctypes.c_int
     lib.orbit_last_stats.argtypes = [ctypes.POINTER(u64), ctypes.c_int]
     lib.orbit_last_stats.restype = ctypes.c_int
     lib.orbit_mlp_init.argtypes = [vp, ctypes.c_uint32, vp]
@@ -157,9 +161,10 @@ def _ptr(t):
 
 
 def _opts(noninduced=False, timing=False, num_wg=0, schedule=SCHED_ID, mlp_weights=None,
-          features_out=None, steps_out=None, groups=0, pass_cycles_out=None, relabel=False):
+          features_out=None, steps_out=None, groups=0, pass_cycles_out=None, relabel=False,
+          serial=False):
     f = (ORB_NONINDUCED if noninduced else 0) | (ORB_TIMING if timing else 0) | \
-        (ORB_RELABEL if relabel else 0)
+        (ORB_RELABEL if relabel else 0) | (ORB_SERIAL_GROUPS if serial else 0)
     g = GROUPS[groups] if isinstance(groups, str) else int(groups)
     return _Opts(f, num_wg, schedule, g, _ptr(mlp_weights), _ptr(features_out), _ptr(steps_out),
                  _ptr(pass_cycles_out))
@@ -190,7 +195,7 @@ class Counter:
 
     def __init__(self, row_ptr, col_idx, k_max=5, noninduced=False, num_wg=0, stream=None,
                  schedule="id", mlp_weights=None, features_out=None, steps_out=None,
-                 groups="auto", pass_cycles_out=None, relabel=False):
+                 groups="auto", pass_cycles_out=None, relabel=False, serial=False):
         """schedule: "id", "static" or "mlp" (source order of the per-source
         kernels; needs mlp_weights, a float32 device tensor of MLP_PARAMS
         values, for "mlp").  features_out (float32 [n, 3]) and steps_out
@@ -209,7 +214,7 @@ class Counter:
         sched = SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule)
         extra = dict(schedule=sched, mlp_weights=mlp_weights, features_out=features_out,
                      steps_out=steps_out, groups=groups, pass_cycles_out=pass_cycles_out,
-                     relabel=relabel)
+                     relabel=relabel, serial=serial)
         self._keep = (mlp_weights, features_out, steps_out, pass_cycles_out)
         self.opts = _opts(noninduced, False, num_wg, **extra)
         self.topts = _opts(noninduced, True, num_wg, **extra)
@@ -236,11 +241,12 @@ class Counter:
 
 
 def count(row_ptr, col_idx, k_max=5, noninduced=False, num_wg=0, groups="auto",
-          relabel=False, overflow_flags=None):
+          relabel=False, overflow_flags=None, serial=False):
     """Orbit counts of one graph as a torch tensor [n, K] on the GPU: int64
     holding the uint64 bits (induced unless noninduced=True).  overflow_flags:
     optional uint8 device tensor [n] for the overflow flags."""
-    c = Counter(row_ptr, col_idx, k_max, noninduced, num_wg, groups=groups, relabel=relabel)
+    c = Counter(row_ptr, col_idx, k_max, noninduced, num_wg, groups=groups, relabel=relabel,
+                serial=serial)
     return c.run(overflow_flags=overflow_flags).clone()
 
 
@@ -340,6 +346,15 @@ def last_phase_times():
     names = (ctypes.c_char_p * 24)()
     k = _lib.orbit_last_phase_times(ms, names, 24)
     return [(names[i].decode(), float(ms[i])) for i in range(k)]
+
+
+def last_kernel_times():
+    """{kernel: ms} of the orbit-group kernels of the last timed call, each
+    timed on its own stream."""
+    ms = (ctypes.c_float * 8)()
+    names = (ctypes.c_char_p * 8)()
+    k = _lib.orbit_last_kernel_times(ms, names, 8)
+    return {names[i].decode(): float(ms[i]) for i in range(k)}
 
 
 def last_stats():
