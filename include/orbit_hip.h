@@ -322,7 +322,9 @@ int orbit_mlp_train(const float *features, const uint64_t *steps, uint32_t count
  * triangles, degeneracy (largest peel level), wedges = sum over vertices of
  * C(d,2), diamonds = sum over edges of C(T(e),2) (the pattern counts W(G)
  * and D(G) in the running-time theorem of the paper's main-theorem
- * section).  Writes up to max_vals values and returns how many. */
+ * section); vals[6] = directed 3-paths i <- j <- k -> l walked by the
+ * 5-cycle procedure (sum over k of d+(k) times the out-degrees of N+(k)).
+ * Writes up to max_vals values and returns how many. */
 int orbit_last_stats(uint64_t *vals, int max_vals);
 
 #ifdef __cplusplus

@@ -3,8 +3,7 @@
 Two builds of the same sources:
 * ``liborbit_hip.so`` -- the library;
 * ``liborbit_hip_tiles.so`` -- the same code with every LDS tile shrunk
-  (clique bit rows, pair-sweep wheel maps, the 5-cycle hash set, the long
-  triangle-list sort), so that graphs small enough for the CPU oracle take
+  (clique bit rows, pair-sweep wheel maps, the long triangle-list sort), so that graphs small enough for the CPU oracle take
   the paths that only hubs of large graphs take in the library build.  Only
   the tests load it.
 """
@@ -21,7 +20,7 @@ SOURCES = ["orbit_lib.hip", "orbit_prep.hip", "orbit_count.hip", "orbit_combine.
            "orbit_sched.hip", "orbit_common.h", "orbit_tables.h"]
 # tile sizes of the test build (each the smallest its kernel accepts or a
 # size a 40..120-vertex graph exceeds)
-SMALL_TILES = {"CLQ_LDS_D": 16, "PAIR_KMAP_LDS": 16, "C5_HSET": 64, "TL_SORT_LDS": 128}
+SMALL_TILES = {"CLQ_LDS_D": 16, "PAIR_KMAP_LDS": 16, "TL_SORT_LDS": 128}
 
 
 def hipcc_command(out: str = LIB, defines=None):

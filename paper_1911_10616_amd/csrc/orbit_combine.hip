@@ -324,18 +324,31 @@ __global__ void __launch_bounds__(WAVE) k_transform(u64 *ni, u32 n, int K, int i
 }
 
 // Work statistics (reported with per-phase timing): wedges = sum of C(d,2)
-// over vertices, diamonds = sum of C(T(e),2) over edges.
-__global__ void k_stats(const u32 *src, const u32 *ci, const u32 *deg, const u32 *T, u32 n,
-                        u64 M2, DevState *st) {
-    u64 w = 0, d = 0;
-    for (u64 u = GTID; u < n; u += GSTRIDE) w += c2((i64)deg[u]);
+// over vertices, diamonds = sum of C(T(e),2) over edges, and the directed
+// 3-paths the 5-cycle kernel walks, i <- j <- k with k -> l for a source l:
+// sum over k of d+(k) * sum_{j in N+(k)} d+(j).
+__global__ void k_stats(const u32 *src, const u32 *ci, const u32 *deg, const u32 *T,
+                        const u64 *out_ptr, const u32 *out_nbr, u32 n, u64 M2, DevState *st) {
+    u64 w = 0, d = 0, p3 = 0;
+    for (u64 u = GTID; u < n; u += GSTRIDE) {
+        w += c2((i64)deg[u]);
+        const u64 b = out_ptr[u], e = out_ptr[u + 1];
+        u64 f = 0;
+        for (u64 q = b; q < e; q++) {
+            const u32 j = out_nbr[q];
+            f += out_ptr[j + 1] - out_ptr[j];
+        }
+        p3 += (e - b) * f;
+    }
     for (u64 s = GTID; s < M2; s += GSTRIDE)
         if (src[s] < ci[s]) d += c2((i64)T[s]);
     w = wave_sum_u64(w);
     d = wave_sum_u64(d);
+    p3 = wave_sum_u64(p3);
     if (lane_id() == 0) {
         atomic_add_u64(&st->wedges, w);
         atomic_add_u64(&st->diamonds, d);
+        atomic_add_u64(&st->paths3, p3);
     }
 }
 

@@ -40,6 +40,7 @@ struct DevState {
     u64 scan_total; // total of the last exclusive scan
     u64 wedges;     // sum over vertices of C(d,2)
     u64 diamonds;   // sum over edges of C(T(e),2)
+    u64 paths3;     // directed 3-paths walked by the 5-cycle kernel
 };
 
 // ---------------------------------------------------------------- binomials

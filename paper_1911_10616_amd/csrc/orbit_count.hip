@@ -1193,12 +1193,25 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
 //   W(i) - [i~k] - [j~l] (removing w = k and w = j), and each non-in-in
 //   wedge l - w - i credits w with P(i) minus the tailed triangles
 //   (Fig. TaileTri): [w->i] Tin(w,l) + [w->l][w->i] (Tmid(w->i) - [l->i]).
+// The sums over 3-paths are grouped by their middle vertex j instead of
+// walking every path: with c(j) = |{k : k -> l, k -> j}| (j != l),
+//   P(i)  = sum over j -> i, j != l, of c(j)                     (i != l)
+//   CI(i) = sum of the corrections [k->i] + [j~l] over the paths to i
+//         = sum_{k -> i, k -> l} (Tmid(k->i) - [l->i]) + sum_{j -> i} c(j) [j~l]
+//           (the j with k -> j -> i are counted by Tmid of the arc k -> i)
+//   credit of j = c(j) (SW(j) - d'(j) [j~l]) - sum_{k -> j, k -> l} (Tout(k->j) - [j->l])
+//   credit of k = sum_{j in N+(k), j != l} (SW(j) - d'(j) [j~l] - Tout(k->j) + [j->l])
+// with SW(j) = sum of W(i) over i in N+(j) \ {l}, d'(j) = |N+(j) \ {l}| and
+// Tout(k->j) = |N+(k) & N+(j)| = T - Tin - Tmid of the arc (i in N+(j) with
+// also k -> i is a triangle above both).  The work per source drops from
+// the number of 3-paths to the out-lists of the distinct middle vertices.
 struct C5Scratch {
-    u32 *Wm;
-    u64 *P, *CI;
-    u32 *touched;
+    u32 *Wm, *C, *touched, *jt;
+    u64 *P, *CI, *TO, *SW;
     unsigned char *mark;
 };
+// Layout (each array 256-aligned): Wm, P, CI | touched | mark | C, TO, SW | jt.
+// The first, third and fourth groups must be zero when a source starts.
 __device__ inline C5Scratch c5_scratch(unsigned char *base, u32 n) {
     C5Scratch c;
     c.Wm = (u32 *)base;
@@ -1206,84 +1219,31 @@ __device__ inline C5Scratch c5_scratch(unsigned char *base, u32 n) {
     c.CI = (u64 *)align256((unsigned char *)(c.P + n));
     c.touched = (u32 *)align256((unsigned char *)(c.CI + n));
     c.mark = align256((unsigned char *)(c.touched + n));
+    c.C = (u32 *)align256(c.mark + n);
+    c.TO = (u64 *)align256((unsigned char *)(c.C + n));
+    c.SW = (u64 *)align256((unsigned char *)(c.TO + n));
+    c.jt = (u32 *)align256((unsigned char *)(c.SW + n));
     return c;
-}
-
-__device__ inline bool out_adjacent(u32 k, u32 i, const u64 *out_ptr, const u32 *out_nbr) {
-    u64 b = out_ptr[k];
-    return bfind(out_nbr + b, (u32)(out_ptr[k + 1] - b), i) != UNSET;
-}
-
-// Per-wave hash set of N+(k) in LDS (open addressing, keys id + 1, 0 =
-// empty), for the test "k -> i" of every directed 3-path through k; used
-// when d+(k) <= C5_HSET / 2, else a binary search in N+(k).
-#ifndef C5_HSET
-#define C5_HSET 1024
-#endif
-static_assert(C5_HSET >= 64 && (C5_HSET & (C5_HSET - 1)) == 0, "C5_HSET: a power of two >= 64");
-constexpr int c5_hset_bits() {
-    int b = 0;
-    while ((1 << b) < C5_HSET) b++;
-    return b;
-}
-// multiplicative hash onto the C5_HSET slots (the top bits of key * 2^32/phi)
-__device__ inline u32 hset_slot(u32 key) { return (key * 2654435761u) >> (32 - c5_hset_bits()); }
-__device__ inline bool hset_build(u32 *hs, u32 k, const u64 *out_ptr, const u32 *out_nbr) {
-    const u64 b = out_ptr[k], e = out_ptr[k + 1];
-    if (e - b > C5_HSET / 2) return false;
-    for (u64 q = b + lane_id(); q < e; q += WAVE) {
-        const u32 key = out_nbr[q] + 1;
-        u32 h = hset_slot(key);
-        for (;;) {  // at most half full: a free slot is always found
-            const u32 old = atomicCAS(&hs[h], 0u, key);
-            if (old == 0u || old == key) break;
-            h = (h + 1) & (C5_HSET - 1);
-        }
-    }
-    wave_sync();
-    return true;
-}
-__device__ inline bool hset_has(const u32 *hs, u32 x) {
-    const u32 key = x + 1;
-    u32 h = hset_slot(key);
-    for (;;) {
-        const u32 v = hs[h];
-        if (v == key) return true;
-        if (v == 0u) return false;
-        h = (h + 1) & (C5_HSET - 1);
-    }
-}
-// Empties the set by clearing exactly the slots of N+(k): each lane finds its
-// own keys (still present, since only it removes them) and zeroes them.
-__device__ inline void hset_clear(u32 *hs, u32 k, const u64 *out_ptr, const u32 *out_nbr) {
-    wave_sync();
-    for (u64 q = out_ptr[k] + lane_id(); q < out_ptr[k + 1]; q += WAVE) {
-        const u32 key = out_nbr[q] + 1;
-        u32 h = hset_slot(key);
-        while (hs[h] != key) h = (h + 1) & (C5_HSET - 1);
-        hs[h] = 0;
-    }
-    wave_sync();
 }
 
 template <class GP>
 __global__ void __launch_bounds__(WG) k_c5(const u32 *rp, const u32 *ci, const u64 *key,
                                           const u64 *out_ptr, const u32 *out_nbr,
-                                          const u32 *Tin, const u32 *Tmid, u32 n,
-                                          unsigned char *scratch, u64 stride, u32 *work,
-                                          const u32 *order, u32 mapn, const u32 *gbase,
-                                          u64 *steps, u64 *cacc, const DevState *st) {
-    __shared__ u32 sh_q_[GP::per_wg][3], sh_nt_[GP::per_wg], sh_next_[GP::per_wg];
+                                          const u32 *out_slot, const u32 *T, const u32 *Tin,
+                                          const u32 *Tmid, u32 n, unsigned char *scratch,
+                                          u64 stride, u32 *work, const u32 *order, u32 mapn,
+                                          const u32 *gbase, u64 *steps, u64 *cacc,
+                                          const DevState *st) {
+    __shared__ u32 sh_q_[GP::per_wg][3], sh_nt_[GP::per_wg], sh_nj_[GP::per_wg],
+        sh_next_[GP::per_wg];
     u32 *sh_q = sh_q_[GP::id()];
     if (GP::rank() == 0) { sh_q[0] = 0; sh_q[1] = 0; }
     u32 &sh_nt = sh_nt_[GP::id()];
+    u32 &sh_nj = sh_nj_[GP::id()];
     u32 &sh_next = sh_next_[GP::id()];
     __shared__ u64 sh_red[WAVES_PER_WG];
     C5Scratch C = c5_scratch(scratch + GP::global_id() * stride, mapn);
-    __shared__ u32 l_hs[WAVES_PER_WG][C5_HSET];
-    for (u32 i = threadIdx.x; i < WAVES_PER_WG * C5_HSET; i += WG) (&l_hs[0][0])[i] = 0;
-    __syncthreads();
-    u32 *hs = l_hs[wave_in_wg()];
+    const u32 lane = lane_id();
     for (;;) {
         const u32 l = next_source<GP>(work, sh_q, order, n, st);
         if (l >= n) break;
@@ -1293,61 +1253,87 @@ __global__ void __launch_bounds__(WG) k_c5(const u32 *rp, const u32 *ci, const u
         const u64 kl = key[l];
         u64 nsteps = 0;  // loop iterations of this thread for this source
         for (u32 i = GP::rank(); i < dl; i += GP::size) C.mark[ci[bl + i] - vb] = 1;
-        if (GP::rank() == 0) { sh_nt = 0; sh_next = 0; }
+        if (GP::rank() == 0) { sh_nt = 0; sh_nj = 0; sh_next = 0; }
         GP::sync();
-        // non-in-in wedges l - w - i, and 3-paths i <- j <- k -> l
+        // pass 1: non-in-in wedges l - w - i; for every in-neighbour k of l,
+        // each out-arc k -> x (x != l): c(x), the Tout part of x's credit,
+        // and the Tmid part of CI(x)
         wave_loop(&sh_next, dl, [&](u32 iw) {
             const u32 w = ci[bl + iw];
             if (key[w] > kl) {  // l -> w, then w -> i
-                for (u64 q = out_ptr[w] + lane_id(); q < out_ptr[w + 1]; q += WAVE) {
+                for (u64 q = out_ptr[w] + lane; q < out_ptr[w + 1]; q += WAVE) {
                     atomicAdd(&C.Wm[out_nbr[q] - vb], 1u);
                     nsteps++;
                 }
-            } else {  // w -> l, then any i ~ w
-                for (u32 s = rp[w] + lane_id(); s < rp[w + 1]; s += WAVE) {
-                    const u32 i = ci[s];
-                    if (i != l) atomicAdd(&C.Wm[i - vb], 1u);
-                    nsteps++;
-                }
-                // w plays k: 3-paths i <- j <- w -> l
-                const u32 k = w;
-                const bool use_hs = hset_build(hs, k, out_ptr, out_nbr);
-                for (u64 qj = out_ptr[k]; qj < out_ptr[k + 1]; qj++) {
-                    const u32 j = out_nbr[qj];
-                    if (j == l) continue;
-                    const u64 jl = C.mark[j - vb];
-                    for (u64 qi = out_ptr[j] + lane_id(); qi < out_ptr[j + 1]; qi += WAVE) {
-                        const u32 i = out_nbr[qi];
-                        nsteps++;
-                        if (i == l) continue;
-                        u64 old = atomicAdd(&C.P[i - vb], 1ull);
-                        if (old == 0) C.touched[atomicAdd(&sh_nt, 1u)] = i;
-                        const bool kin = use_hs ? hset_has(hs, i) : out_adjacent(k, i, out_ptr, out_nbr);
-                        atomic_add_u64(&C.CI[i - vb], (kin ? 1 : 0) + jl);
-                    }
-                }
-                if (use_hs) hset_clear(hs, k, out_ptr, out_nbr);
+                return;
+            }
+            // w -> l, then any i ~ w
+            for (u32 s = rp[w] + lane; s < rp[w + 1]; s += WAVE) {
+                const u32 i = ci[s];
+                if (i != l) atomicAdd(&C.Wm[i - vb], 1u);
+                nsteps++;
+            }
+            const u32 k = w;
+            for (u64 q = out_ptr[k] + lane; q < out_ptr[k + 1]; q += WAVE) {
+                const u32 x = out_nbr[q];
+                nsteps++;
+                if (x == l) continue;
+                const u32 s = out_slot[q];
+                const u32 ts = T[s], ti = Tin[s], tm = Tmid[s];
+                const bool adj = C.mark[x - vb] != 0;
+                const u64 kx = key[x];
+                const u32 xl = adj && kx < kl, lx = adj && kx > kl;  // x -> l, l -> x
+                if (atomicAdd(&C.C[x - vb], 1u) == 0) C.jt[atomicAdd(&sh_nj, 1u)] = x;
+                const u64 to = (u64)(ts - ti - tm) - xl;
+                if (to) atomicAdd(&C.TO[x - vb], to);
+                const u64 cm = (u64)tm - lx;
+                if (cm) atomicAdd(&C.CI[x - vb], cm);
             }
         });
         GP::sync();
         if (GP::rank() == 0) sh_next = 0;
         GP::sync();
-        // credits of j and k per 3-path, and of w per wedge
+        // pass 1b: every middle vertex j reached: P(i) += c(j) and
+        // CI(i) += c(j) [j~l] for i in N+(j) \ {l}; SW(j); credit of j
+        const u32 nj = sh_nj;
+        wave_loop(&sh_next, nj, [&](u32 t) {
+            const u32 j = C.jt[t];
+            const u64 cj = C.C[j - vb];
+            const bool mj = C.mark[j - vb] != 0;
+            u64 sw = 0, dj = 0;
+            for (u64 q = out_ptr[j] + lane; q < out_ptr[j + 1]; q += WAVE) {
+                const u32 i = out_nbr[q];
+                nsteps++;
+                if (i == l) continue;
+                if (atomicAdd(&C.P[i - vb], cj) == 0) C.touched[atomicAdd(&sh_nt, 1u)] = i;
+                if (mj) atomicAdd(&C.CI[i - vb], cj);
+                sw += C.Wm[i - vb];
+                dj++;
+            }
+            sw = wave_sum_u64(sw);
+            dj = wave_sum_u64(dj);
+            if (lane == 0) {
+                C.SW[j - vb] = sw;
+                atomic_add_u64(&cacc[j], cj * (sw - (mj ? dj : 0)) - C.TO[j - vb]);
+            }
+        });
+        GP::sync();
+        if (GP::rank() == 0) sh_next = 0;
+        GP::sync();
+        // pass 2: credits of w per wedge, and of k per out-arc k -> j
         wave_loop(&sh_next, dl, [&](u32 iw) {
             const u32 slw = bl + iw;
             const u32 w = ci[slw];
             const u64 kw = key[w];
+            const u64 tin = Tin[slw];
             u64 accw = 0;
             if (kw > kl) {  // l -> w -> i
-                const u64 tin = Tin[slw];
-                for (u64 q = out_ptr[w] + lane_id(); q < out_ptr[w + 1]; q += WAVE) {
-                    const u32 i = out_nbr[q];
-                    const u64 p = C.P[i - vb];
+                for (u64 q = out_ptr[w] + lane; q < out_ptr[w + 1]; q += WAVE) {
+                    const u64 p = C.P[out_nbr[q] - vb];
                     if (p) accw += p - tin;  // w -> i holds; w -> l does not
                 }
             } else {  // w -> l
-                const u64 tin = Tin[slw];
-                for (u32 s = rp[w] + lane_id(); s < rp[w + 1]; s += WAVE) {
+                for (u32 s = rp[w] + lane; s < rp[w + 1]; s += WAVE) {
                     const u32 i = ci[s];
                     if (i == l) continue;
                     const u64 p = C.P[i - vb];
@@ -1359,30 +1345,24 @@ __global__ void __launch_bounds__(WG) k_c5(const u32 *rp, const u32 *ci, const u
                     }
                     accw += p - corr;
                 }
-                // 3-paths through k = w: credits of j and k
+                // w plays k: its out-arcs k -> j, j != l
                 const u32 k = w;
-                const bool use_hs = hset_build(hs, k, out_ptr, out_nbr);
                 u64 acck = 0;
-                for (u64 qj = out_ptr[k]; qj < out_ptr[k + 1]; qj++) {
-                    const u32 j = out_nbr[qj];
+                for (u64 q = out_ptr[k] + lane; q < out_ptr[k + 1]; q += WAVE) {
+                    const u32 j = out_nbr[q];
                     if (j == l) continue;
-                    const u64 jl = C.mark[j - vb];
-                    u64 accj = 0;
-                    for (u64 qi = out_ptr[j] + lane_id(); qi < out_ptr[j + 1]; qi += WAVE) {
-                        const u32 i = out_nbr[qi];
-                        if (i == l) continue;
-                        const bool kin = use_hs ? hset_has(hs, i) : out_adjacent(k, i, out_ptr, out_nbr);
-                        accj += (u64)C.Wm[i - vb] - (kin ? 1 : 0) - jl;
-                    }
-                    accj = wave_sum_u64(accj);
-                    if (lane_id() == 0) atomic_add_u64(&cacc[j], accj);
-                    acck += accj;
+                    const u32 s = out_slot[q];
+                    const bool mj = C.mark[j - vb] != 0;
+                    const u32 jl = mj && key[j] < kl;  // j -> l
+                    const u64 dj = (out_ptr[j + 1] - out_ptr[j]) - jl;
+                    const u64 tout = (u64)T[s] - Tin[s] - Tmid[s];
+                    acck += C.SW[j - vb] - (mj ? dj : 0) - tout + jl;
                 }
-                if (lane_id() == 0) atomic_add_u64(&cacc[k], acck);
-                if (use_hs) hset_clear(hs, k, out_ptr, out_nbr);
+                acck = wave_sum_u64(acck);
+                if (lane == 0) atomic_add_u64(&cacc[k], acck);
             }
             accw = wave_sum_u64(accw);
-            if (lane_id() == 0) atomic_add_u64(&cacc[w], accw);
+            if (lane == 0) atomic_add_u64(&cacc[w], accw);
         });
         GP::sync();
         // credits of i (summed over its 3-paths) and of l
@@ -1401,19 +1381,27 @@ __global__ void __launch_bounds__(WG) k_c5(const u32 *rp, const u32 *ci, const u
             if (GP::rank() == 0) steps[l] += tot;
         }
         GP::sync();
-        // reset: Wm was touched on every wedge endpoint, P/CI on 3-path ends
+        // reset: P, CI of the 3-path ends; C, TO, SW of the middle vertices;
+        // Wm of every wedge end
         for (u32 t = GP::rank(); t < nt; t += GP::size) {
             const u32 i = C.touched[t];
-            C.P[i - vb] = 0; C.CI[i - vb] = 0;
+            C.P[i - vb] = 0;
+            C.CI[i - vb] = 0;
+        }
+        for (u32 t = GP::rank(); t < nj; t += GP::size) {
+            const u32 j = C.jt[t];
+            C.C[j - vb] = 0;
+            C.TO[j - vb] = 0;
+            C.SW[j - vb] = 0;
         }
         if (GP::rank() == 0) sh_next = 0;
         GP::sync();
         wave_loop(&sh_next, dl, [&](u32 iw) {
             const u32 w = ci[bl + iw];
             if (key[w] > kl) {
-                for (u64 q = out_ptr[w] + lane_id(); q < out_ptr[w + 1]; q += WAVE) C.Wm[out_nbr[q] - vb] = 0;
+                for (u64 q = out_ptr[w] + lane; q < out_ptr[w + 1]; q += WAVE) C.Wm[out_nbr[q] - vb] = 0;
             } else {
-                for (u32 s = rp[w] + lane_id(); s < rp[w + 1]; s += WAVE) C.Wm[ci[s] - vb] = 0;
+                for (u32 s = rp[w] + lane; s < rp[w + 1]; s += WAVE) C.Wm[ci[s] - vb] = 0;
             }
         });
         for (u32 i = GP::rank(); i < dl; i += GP::size) C.mark[ci[bl + i] - vb] = 0;

@@ -28,7 +28,7 @@ const u32 kRelabelSortWg = 64;     // workgroups sorting the long rows of a rela
 thread_local float g_phase_ms[kMaxPhases];
 thread_local const char *g_phase_name[kMaxPhases];
 thread_local int g_nphase = 0;
-thread_local u64 g_stats[6];
+thread_local u64 g_stats[7];
 
 struct Buf {
     u64 off = 0, bytes = 0;
@@ -111,9 +111,10 @@ u64 pair_stride(u32 n, bool wave_maps) {
     return 3 * align_up(8ull * n, 256) + align_up(4ull * n, 256) +
            (wave_maps ? 2 * align_up(4ull * WAVES_PER_WG * n, 256) : 0) + 256;
 }
-// 5-cycles: Wm (u32), P, CI (u64), touched (u32), mark (u8)
+// 5-cycles: Wm (u32), P, CI (u64), touched (u32), mark (u8), C (u32), TO, SW
+// (u64), jt (u32)
 u64 c5_stride(u32 n) {
-    return 2 * align_up(4ull * n, 256) + 2 * align_up(8ull * n, 256) + align_up(n, 256) + 256;
+    return 4 * align_up(4ull * n, 256) + 4 * align_up(8ull * n, 256) + align_up(n, 256) + 256;
 }
 u64 clique_stride(u32 dmax) {
     u64 W = (dmax + 63) / 64;
@@ -236,9 +237,9 @@ int zero_ranges(int which, u32 n, bool wave_maps, ZeroRange *r) {
         r[1] = {3 * a8 + a4, align_up(4ull * WAVES_PER_WG * n, 256)};
         return 2;
     }
-    // 5-cycles: Wm, P, CI, (touched), mark
+    // 5-cycles: Wm, P, CI, (touched), mark, C, TO, SW, (jt)
     r[0] = {0, a4 + 2 * a8};
-    r[1] = {a4 + 2 * a8 + a4, a1};
+    r[1] = {a4 + 2 * a8 + a4, a1 + a4 + 2 * a8};
     return 2;
 }
 
@@ -821,7 +822,7 @@ int count_impl(const u32 *rp, const u32 *ci, u32 n, u64 m, const u64 *vptr, u32 
         if (rc) return rc;
         if (!conc) tm.mark("zero_c5");
         tm.kbegin(1, sb);
-        WITH_GP(wave_groups, k_c5<GPT><<<c5_wg, WG, 0, sb>>>(rp, ci, key, outptr, outnbr, Tin, Tmid, n, scr_c5,
+        WITH_GP(wave_groups, k_c5<GPT><<<c5_wg, WG, 0, sb>>>(rp, ci, key, outptr, outnbr, outslot, T, Tin, Tmid, n, scr_c5,
                                   L.stride_c5, work + wi++, order, mapn, gbase, steps_out, cacc, st));
         HCHK(hipGetLastError());
         tm.kend(1, sb);
@@ -845,7 +846,8 @@ int count_impl(const u32 *rp, const u32 *ci, u32 n, u64 m, const u64 *vptr, u32 
     HCHK(hipGetLastError());
     tm.mark("combine");
     if (flags & ORB_TIMING) {
-        k_stats<<<grid_for(M2 > n ? M2 : n, WG), WG, 0, s>>>(src, ci, deg, T, n, M2, st);
+        k_stats<<<grid_for(M2 > n ? M2 : n, WG), WG, 0, s>>>(src, ci, deg, T, outptr, outnbr, n,
+                                                             M2, st);
         HCHK(hipGetLastError());
     }
     if (cap) {  // the replay checks that it saw the sizes it was built for
@@ -858,7 +860,7 @@ int count_impl(const u32 *rp, const u32 *ci, u32 n, u64 m, const u64 *vptr, u32 
     tm.finish();
     if (flags & ORB_TIMING) {
         g_stats[0] = n; g_stats[1] = m; g_stats[2] = ntri; g_stats[3] = hs.maxlevel;
-        g_stats[4] = hs.wedges; g_stats[5] = hs.diamonds;
+        g_stats[4] = hs.wedges; g_stats[5] = hs.diamonds; g_stats[6] = hs.paths3;
     }
     if (hs.err) return err_to_status(hs.err);
     return ORB_OK;
@@ -1239,7 +1241,7 @@ const char *orbit_strerror(int status) {
 }
 
 int orbit_last_stats(uint64_t *vals, int max_vals) {
-    int k = max_vals < 6 ? max_vals : 6;
+    int k = max_vals < 7 ? max_vals : 7;
     for (int i = 0; i < k; i++) vals[i] = g_stats[i];
     return k;
 }

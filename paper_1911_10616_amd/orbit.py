@@ -359,9 +359,9 @@ def last_kernel_times():
 
 def last_stats():
     """Work statistics of the last timed call (dict)."""
-    v = (ctypes.c_uint64 * 6)()
-    k = _lib.orbit_last_stats(v, 6)
-    keys = ("n", "m", "triangles", "degeneracy", "wedges", "diamonds")
+    v = (ctypes.c_uint64 * 7)()
+    k = _lib.orbit_last_stats(v, 7)
+    keys = ("n", "m", "triangles", "degeneracy", "wedges", "diamonds", "paths3")
     return {keys[i]: int(v[i]) for i in range(k)}
 
 

@@ -1,11 +1,12 @@
 """GPU regression tests of the paths that only large graphs reach.
 
 * The small-tile build (every LDS tile shrunk) on oracle-sized graphs:
-  global clique bit rows, global wheel maps, the 5-cycle out-list search,
+  global clique bit rows, wheel maps in LDS windows and in global memory,
   the LDS and bitmap sorts of long triangle lists.
-* The library build on graphs with those features at full size: a vertex
-  of out-degree 520 (the 5-cycle kernel's out-list search), a star whose
-  centre count C(s,4) wraps modulo 2^64, and the overflow flags.
+* The library build on graphs with those features at full size: vertices
+  of out-degree 520 (clique rows in global memory, long out-lists in the
+  5-cycle kernel), a star whose centre count C(s,4) wraps modulo 2^64, and
+  the overflow flags.
 * Replaying a plan on a changed input reports an error and writes nothing
   out of bounds.
 
@@ -120,9 +121,9 @@ def _family_counts(a, make, rows, ks):
     return out
 
 
-def test_c5_outlist_search_at_outdegree_520(orbit):
-    """Out-degree 520 > 512: the 5-cycle kernel tests k -> i by a search of
-    N+(k) instead of its LDS hash set."""
+def test_outdegree_520(orbit):
+    """Out-degree 520: clique rows beyond the LDS tile, 5-cycle middle
+    vertices with long out-lists, against oracle counts of the family."""
     a = 520
     rp, ci = _bip_matching(a)
     _say("K_{520,520} + matching")

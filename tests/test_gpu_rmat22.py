@@ -1,0 +1,146 @@
+"""R-MAT scale 22 (edge factor 16, (0.57, 0.19, 0.19, 0.05), symmetrised and
+deduplicated: 4.2M vertices, 64M edges) at full size, checked through
+properties that hold at any size -- the oracle cannot enumerate the
+neighbourhoods of its hubs (the largest has about 160,000 neighbours).
+
+* orbit 0 is the degree; I2 + I3 = C(d,2); I1 + 2 I3 = sum_{v~u} (d(v) - 1);
+* the non-induced star orbits A I equal C(d,3), C(d,4), sum C(d(v)-1, 2),
+  sum C(d(v)-1, 3) -- modulo 2^64: the largest hub's C(d,4) exceeds 2^64, so
+  this graph also checks the wrap-around of the whole pipeline;
+* per pattern, sum_u I_o(u) / |o| agrees across its orbits (modulo 2^64);
+* the overflow flags equal the oracle's fp64 bound, and the flagged rows are
+  exactly the vertices whose bound reaches 2^63.
+
+A thread prints the elapsed time every 30 s while the library call runs.
+"""
+import json
+import os
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1911_10616_amd import graphgen as gg
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+U = np.uint64
+M64 = 1 << 64
+
+
+class _Heartbeat:
+    def __init__(self, what):
+        self.what, self.t0, self.stop = what, time.time(), threading.Event()
+        self.th = threading.Thread(target=self._run, daemon=True)
+
+    def _run(self):
+        while not self.stop.wait(30):
+            print(f"  ... {self.what}: {time.time() - self.t0:.0f} s", flush=True)
+
+    def __enter__(self):
+        self.th.start()
+        return self
+
+    def __exit__(self, *a):
+        self.stop.set()
+        self.th.join()
+
+
+@pytest.fixture(scope="module")
+def setup():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1911_10616_amd import orbit
+    with _Heartbeat("generating R-MAT 22"):
+        rp, ci = gg.workload("rmat22")
+    n = len(rp) - 1
+    print("rmat22 generated", n, ci.size // 2, flush=True)
+    flags = torch.empty(n, dtype=torch.uint8, device="cuda")
+    with _Heartbeat("counting R-MAT 22"):
+        c = orbit.Counter(rp, ci, 5, schedule="static")
+        t0 = time.time()
+        out = c.run(timing=True, overflow_flags=flags)
+        torch.cuda.synchronize()
+        wall = time.time() - t0
+    rec = {"wall_s": wall, "ws_bytes": c.ws_bytes, "phases_ms": dict(orbit.last_phase_times()),
+           "kernels_ms": orbit.last_kernel_times(), "work": orbit.last_stats()}
+    print("rmat22 counted", json.dumps(rec), flush=True)
+    os.makedirs("gpurun_out", exist_ok=True)
+    with open(os.path.join("gpurun_out", "rmat22_run.json"), "w") as f:
+        json.dump(rec, f)
+    sums, pats, _ = orbit.voc_summary(out, 5)
+    counts = out.cpu().numpy().view(U).copy()
+    f = flags.cpu().numpy().copy()
+    del c, out, flags
+    torch.cuda.empty_cache()
+    return rp, ci, counts, f, sums, pats
+
+
+def _binom_mod(x, k):
+    """C(x, k) modulo 2^64 for a uint64 array (exact integers)."""
+    x = np.asarray(x, dtype=U)
+    out = np.zeros_like(x)
+    small = x < U(1 << 15)
+    xs = x[small]
+    prod = np.ones_like(xs)
+    for i in range(k):
+        prod = prod * np.where(xs >= U(i), xs - U(i), U(0))
+    out[small] = prod // U([1, 1, 2, 6, 24][k])
+    from math import comb
+    for j in np.flatnonzero(~small):
+        out[j] = U(comb(int(x[j]), k) % M64)
+    return out
+
+
+def _row_sums(rp, vals):
+    cs = np.zeros(vals.size + 1, dtype=U)
+    np.cumsum(vals.astype(U), out=cs[1:])
+    return cs[rp[1:].astype(np.int64)] - cs[rp[:-1].astype(np.int64)]
+
+
+def test_degree_identities(setup):
+    rp, ci, I, _, _, _ = setup
+    d = np.diff(rp).astype(U)
+    np.testing.assert_array_equal(I[:, 0], d)
+    assert np.array_equal(I[:, 2] + I[:, 3], _binom_mod(d, 2))
+    nb = d[ci.astype(np.int64)]
+    assert np.array_equal(I[:, 1] + U(2) * I[:, 3], _row_sums(rp, nb - U(1)))
+
+
+def test_star_orbits_modulo_2_64(setup):
+    rp, ci, I, _, _, _ = setup
+    A = oracle.transform_matrix().astype(U)
+    d = np.diff(rp).astype(U)
+    nb = d[ci.astype(np.int64)]
+
+    def noninduced(o):
+        return (I * A[o][None, :]).sum(axis=1, dtype=U)
+    assert int(d.max()) > 145_056  # C(d,4) of the largest hub is >= 2^64
+    assert np.array_equal(noninduced(7), _binom_mod(d, 3))
+    assert np.array_equal(noninduced(23), _binom_mod(d, 4))
+    assert np.array_equal(noninduced(6), _row_sums(rp, _binom_mod(nb - U(1), 2)))
+    assert np.array_equal(noninduced(22), _row_sums(rp, _binom_mod(nb - U(1), 3)))
+
+
+def test_pattern_copies_agree_across_orbits(setup):
+    _, _, I, _, sums, pats = setup
+    t = oracle.tables()
+    g = np.asarray(t["orbit_graphlet"])
+    size = [int(x) for x in t["orbit_size"]]
+    tot = I.sum(axis=0, dtype=U)
+    assert [int(x) for x in tot] == [s % M64 for s in sums]
+    for pat in np.unique(g):
+        orbs = np.flatnonzero(g == pat)
+        for o1, o2 in zip(orbs[:-1], orbs[1:]):
+            assert (sums[o1] * size[o2] - sums[o2] * size[o1]) % M64 == 0, (pat, o1, o2)
+
+
+def test_overflow_flags(setup):
+    rp, ci, _, f, _, _ = setup
+    ref = oracle.overflow_flags(rp, ci)
+    np.testing.assert_array_equal(f, ref)
+    d = np.diff(rp.astype(np.int64))
+    assert f[np.argmax(d)] == 1
+    print("flagged rows", int(f.sum()), "of", len(f), flush=True)
