@@ -440,7 +440,7 @@ __global__ void __launch_bounds__(WG) k_c4(const u32 *rp, const u32 *ci, const u
 //   pass 2: orbit 70, sum over 4-cliques containing u of K4(opposite
 //           triangle) - 1 (Theorem 5vertexorbit), needing the final K4(t).
 #ifndef CLQ_LDS_D
-#define CLQ_LDS_D 384
+#define CLQ_LDS_D 1024
 #endif
 // u64 words of one execution group's LDS rows for out-degrees up to d
 __host__ __device__ inline u64 clique_lds_words(u32 d) {

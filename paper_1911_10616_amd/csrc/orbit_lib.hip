@@ -23,7 +23,7 @@ const int kMaxPhases = 24;
 // (bounded by the degeneracy) this small, i.e. when every source is light
 const u32 kWaveGroupMaxMap = 4096;
 const u32 kWaveGroupMaxOut = 64;
-const u64 kMaxDynLds = 64 << 10;  // dynamic LDS per workgroup
+const u64 kMaxDynLds = 156 << 10;  // dynamic LDS per workgroup (160 KB per workgroup on gfx950)
 const u32 kRelabelSortWg = 64;     // workgroups sorting the long rows of a relabelled CSR
 thread_local float g_phase_ms[kMaxPhases];
 thread_local const char *g_phase_name[kMaxPhases];

@@ -90,8 +90,8 @@ def test_special_graphs(orbit, name, make):
 
 
 def test_hub_larger_than_lds_tile(orbit):
-    # a 4-core-rich graph whose out-degrees exceed the clique kernel's LDS
-    # tile (384), exercising the global-memory bit rows
+    # K420: out-degrees up to 419, clique bit rows of 7 words per row (the
+    # global-memory rows of larger out-degrees run in the small-tile build)
     rp, ci = gg.complete(420)
     _say("K420")
     got = orbit.count_np(rp, ci, 5)
