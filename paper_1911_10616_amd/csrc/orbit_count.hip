@@ -429,11 +429,17 @@ __global__ void __launch_bounds__(WG) k_c4(const u32 *rp, const u32 *ci, const u
 }
 
 // ---- 4- and 5-cliques.  For a source a, G+(a) is the graph induced on its
-// out-neighbours; its adjacency is held as bit rows (und: undirected, outm:
-// oriented).  Every clique is counted once from its lowest-ranked vertex a:
-// triangle records (a,b,c) give the 4-clique apexes inside N+(a) as
-// und[b] & und[c] (and oriented ones as outm[b] & outm[c]); 5-cliques are
-// oriented 4-clique apexes of those.
+// out-neighbours; its adjacency is held as bit rows (outm: out-neighbours,
+// inm: in-neighbours within G+(a); the undirected row is their union).
+// Every clique is counted once from its lowest-ranked vertex a: triangle
+// records (a,b,c) give the 4-clique apexes inside N+(a) as (outm | inm)[b]
+// & (outm | inm)[c] (and oriented ones as outm[b] & outm[c]); 5-cliques are the 4-cliques of
+// G+(a).  Each oriented triangle x < y < z of G+(a) (a 4-clique a,x,y,z)
+// credits x, y and z with up = |outm[x] & outm[y] & outm[z]| (the 4-cliques
+// of G+(a) it is the bottom of) and z also with down = |inm[x] & inm[y] &
+// inm[z]| (those it is the top of), so every member of every 4-clique of
+// G+(a) -- every 5-clique through a -- is credited once without visiting
+// the 5-cliques one by one.
 //   pass 1: K4(u) (orbit 14), K4(e) (edge orbit E11), K4(t) per triangle
 //           (apexes inside N+(a) plus one credit from each 4-clique whose
 //           lowest vertex precedes the triangle), 5-cliques (orbit 72).
@@ -487,12 +493,12 @@ __global__ void __launch_bounds__(WG) k_clique(int pass, u32 n, const u32 *rev,
     if (GP::rank() == 0) { sh_q[0] = 0; sh_q[1] = 0; }
     u32 &sh_next = sh_next_[GP::id()];
     __shared__ u64 sh_red[WAVES_PER_WG];
-    // dynamic LDS: acc, acc5 [lds_d]; und, outm [lds_d * lds_w]; nbr [lds_d]
+    // dynamic LDS: acc, acc5 [lds_d]; inm, outm [lds_d * lds_w]; nbr [lds_d]
     // (one such set per execution group)
     extern __shared__ u64 dyn_lds[];
     const u32 lds_w = (lds_d + 63) / 64;
     u64 *l_acc = dyn_lds + (u64)GP::id() * clique_lds_words(lds_d), *l_acc5 = l_acc + lds_d;
-    u64 *l_und = l_acc5 + lds_d, *l_out = l_und + (u64)lds_d * lds_w;
+    u64 *l_inm = l_acc5 + lds_d, *l_out = l_inm + (u64)lds_d * lds_w;
     u32 *l_nbr = (u32 *)(l_out + (u64)lds_d * lds_w);
     unsigned char *gbase = scratch + GP::global_id() * stride;
     for (;;) {
@@ -503,17 +509,17 @@ __global__ void __launch_bounds__(WG) k_clique(int pass, u32 n, const u32 *rev,
         if (D < 2) continue;
         const u32 W = (D + 63) / 64;
         u32 *nbr;
-        u64 *und, *outm, *acc, *acc5;
+        u64 *inm, *outm, *acc, *acc5;
         if (D <= lds_d) {
-            nbr = l_nbr; und = l_und; outm = l_out; acc = l_acc; acc5 = l_acc5;
+            nbr = l_nbr; inm = l_inm; outm = l_out; acc = l_acc; acc5 = l_acc5;
         } else {
             if (D > dcap) {  // cannot happen: out-degrees are bounded by the peel level
                 if (GP::rank() == 0) atomicOr(&st->err, ERRB_INTERNAL);
                 continue;
             }
             nbr = (u32 *)gbase;
-            und = (u64 *)align256((unsigned char *)(nbr + D));
-            outm = und + (u64)D * W;
+            inm = (u64 *)align256((unsigned char *)(nbr + D));
+            outm = inm + (u64)D * W;
             acc = outm + (u64)D * W;
             acc5 = acc + D;
         }
@@ -522,10 +528,10 @@ __global__ void __launch_bounds__(WG) k_clique(int pass, u32 n, const u32 *rev,
             acc[i] = 0;
             acc5[i] = 0;
         }
-        // the undirected rows serve the 4-clique popcounts of pass 1 only
+        // the in-rows serve pass 1 only
         for (u32 i = GP::rank(); i < D * W; i += GP::size) {
             outm[i] = 0;
-            if (pass == 1) und[i] = 0;
+            if (pass == 1) inm[i] = 0;
         }
         if (GP::rank() == 0) sh_next = 0;
         GP::sync();
@@ -535,10 +541,7 @@ __global__ void __launch_bounds__(WG) k_clique(int pass, u32 n, const u32 *rev,
                 u32 j = bfind(nbr, D, out_nbr[q]);
                 if (j != UNSET) {
                     atomicOr(&outm[(u64)i * W + j / 64], 1ull << (j % 64));
-                    if (pass == 1) {
-                        atomicOr(&und[(u64)i * W + j / 64], 1ull << (j % 64));
-                        atomicOr(&und[(u64)j * W + i / 64], 1ull << (i % 64));
-                    }
+                    if (pass == 1) atomicOr(&inm[(u64)j * W + i / 64], 1ull << (i % 64));
                 }
             }
         });
@@ -556,11 +559,12 @@ __global__ void __launch_bounds__(WG) k_clique(int pass, u32 n, const u32 *rev,
             const u32 c = tri_c[r];
             const u32 j = bfind(nbr, D, c);
             if (j == UNSET) { atomicOr(&st->err, ERRB_INTERNAL); continue; }
-            const u64 *ri = und + (u64)i * W, *rj = und + (u64)j * W;
+            const u64 *ri = inm + (u64)i * W, *rj = inm + (u64)j * W;
             const u64 *oi = outm + (u64)i * W, *oj = outm + (u64)j * W;
             if (pass == 1) {
+                // the undirected row is out | in
                 u32 k = 0;
-                for (u32 w = 0; w < W; w++) k += __popcll(ri[w] & rj[w]);
+                for (u32 w = 0; w < W; w++) k += __popcll((ri[w] | oi[w]) & (rj[w] | oj[w]));
                 if (k) {
                     atomicAdd(&K4t[r], k);
                     u32 sbc = tri_sbc[r];
@@ -586,23 +590,19 @@ __global__ void __launch_bounds__(WG) k_clique(int pass, u32 n, const u32 *rev,
                         }
                         // the triangle (b,c,d) gets this 4-clique as an apex a
                         atomicAdd(&K4t[cbc.find(d, tri_c, st)], 1u);
-                        const u64 *ol = outm + (u64)l * W;
-                        u32 c5 = 0;
-                        for (u32 w2 = 0; w2 < W; w2++) c5 += __popcll(oi[w2] & oj[w2] & ol[w2]);
-                        if (c5) {
-                            tot5 += c5;
-                            atomicAdd(&acc5[i], (u64)c5);
-                            atomicAdd(&acc5[j], (u64)c5);
-                            atomicAdd(&acc5[l], (u64)c5);
-                            for (u32 w2 = 0; w2 < W; w2++) {
-                                u64 m5 = oi[w2] & oj[w2] & ol[w2];
-                                while (m5) {
-                                    u32 e = w2 * 64 + __ffsll((long long)m5) - 1;
-                                    m5 &= m5 - 1;
-                                    atomicAdd(&acc5[e], 1ull);
-                                }
-                            }
+                        // the oriented triangle (i, j, l) of G+(a): up / down
+                        const u64 *ol = outm + (u64)l * W, *il = inm + (u64)l * W;
+                        u32 up = 0, down = 0;
+                        for (u32 w2 = 0; w2 < W; w2++) {
+                            up += __popcll(oi[w2] & oj[w2] & ol[w2]);
+                            down += __popcll(ri[w2] & rj[w2] & il[w2]);
                         }
+                        if (up) {
+                            tot5 += up;
+                            atomicAdd(&acc5[i], (u64)up);
+                            atomicAdd(&acc5[j], (u64)up);
+                        }
+                        if (up + down) atomicAdd(&acc5[l], (u64)(up + down));
                     }
                 }
             } else {
