@@ -55,38 +55,89 @@ def train_cost_model(orbit, seed=1, iters=1500, batch=4096):
     return w, loss
 
 
-def cpu_baseline(rp, ci, seconds: float, seed: int = 1):
-    """The CPU oracle (rooted enumeration) timed on a bounded sample of the
-    same graph, scaled to edges/s by extrapolating the time per vertex."""
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(rp, ci, budget: int = 20_000, per_stratum: int = 2, seed: int = 1):
+    """The CPU oracle timed on the host cores on a degree-stratified sample
+    of the same graph: per degree decile `per_stratum` seeded vertices,
+    each enumerated by the oracle's rooted count (every connected 2..5-vertex
+    subset containing it) on one thread, up to `budget` subsets; the vertices
+    run in parallel on the cores.  The full-graph time is extrapolated
+    stratum by stratum (decile size x mean time per sampled vertex) and
+    divided by the cores; a vertex cut off at the budget contributes its
+    time so far, so with any cut-off the rate is an upper bound.  Also the
+    full oracle on the small Erdos-Renyi workload (it finishes there):
+    median of 3 runs on one thread and on all the cores."""
     import oracle
-    threads = min(16, os.cpu_count() or 1)
+    from concurrent.futures import ThreadPoolExecutor
+    from paper_1911_10616_amd import graphgen as gg
+    cores = min(16, os.cpu_count() or 1)
     n = len(rp) - 1
     m = ci.size // 2
+    d = np.diff(rp.astype(np.int64))
+    order = np.argsort(d, kind="stable")
     rng = np.random.Generator(np.random.PCG64(seed))
-    order = rng.permutation(n).astype(np.uint32)
-    budget = 50_000
-    done = 0
-    complete = 0
+    strata = np.array_split(order, 10)
+    picks = [(s, int(v)) for s, part in enumerate(strata)
+             for v in rng.choice(part, size=min(per_stratum, part.size), replace=False)]
+
+    def one(v):
+        t = time.perf_counter()
+        _, comp = oracle.rooted_counts(rp, ci, [v], kmax=5, budget=budget, threads=1)
+        return time.perf_counter() - t, bool(comp[0])
     t0 = time.perf_counter()
-    batch = threads
-    while time.perf_counter() - t0 < seconds and done < n:
-        roots = order[done:done + batch]
-        _, comp = oracle.rooted_counts(rp, ci, roots, kmax=5, budget=budget, threads=threads)
-        done += roots.size
-        complete += int(comp.sum())
-    el = time.perf_counter() - t0
-    per_vertex = el / max(done, 1)
-    est_full = per_vertex * n
+    with ThreadPoolExecutor(max_workers=cores) as ex:
+        res = list(ex.map(one, [v for _, v in picks]))
+    wall = time.perf_counter() - t0
+    est = 0.0
+    per = []
+    for s, part in enumerate(strata):
+        ts = [r[0] for (ss, _), r in zip(picks, res) if ss == s]
+        done = sum(r[1] for (ss, _), r in zip(picks, res) if ss == s)
+        est += part.size * (sum(ts) / max(len(ts), 1))
+        per.append({"degrees": [int(d[part[0]]), int(d[part[-1]])], "sampled": len(ts),
+                    "finished": done, "mean_s": round(sum(ts) / max(len(ts), 1), 4)})
+    finished = sum(r[1] for r in res)
+    full_s = est / cores
+    # the full oracle where it finishes: Erdos-Renyi G(2000, 0.005)
+    erp, eci = gg.workload("er2000")
+    em = eci.size // 2
+    def timed(threads):
+        ts = []
+        for _ in range(3):
+            t = time.perf_counter()
+            oracle.induced_counts(erp, eci, threads=threads)
+            ts.append(time.perf_counter() - t)
+        return float(np.median(ts))
+    t1, tc = timed(1), timed(cores)
     return {
-        "value": m / est_full,
+        "value": round(m / full_s, 3),
         "unit": "edges/s",
-        "cores": threads,
+        "cores": cores,
         "kind": "oracle",
-        "sample": (f"{done} uniformly sampled vertices, rooted enumeration of every connected "
-                   f"2..5-vertex subset containing the vertex, at most {budget} subsets each "
-                   f"({complete} finished within that budget, the rest were cut off, so the "
-                   f"extrapolated CPU rate is an upper bound); {el:.1f} s on {threads} threads, "
-                   f"scaled by n/{done}"),
+        "sample": (f"{len(picks)} vertices, {per_stratum} per degree decile (seeded), each the "
+                   f"oracle's rooted enumeration of every connected 2..5-vertex subset containing "
+                   f"it, at most {budget:.0e} subsets, one thread per vertex on {cores} cores "
+                   f"({wall:.1f} s); {finished} of {len(picks)} finished within the budget, so the "
+                   f"rate is an upper bound (a cut-off vertex counts its time so far); full time "
+                   f"= sum over deciles of size x mean time, divided by the cores"),
+        "cpu_model": _cpu_model(),
+        "nproc": os.cpu_count(),
+        "coverage": round(finished / len(picks), 3),
+        "extrapolated_full_s": round(full_s, 1),
+        "strata": per,
+        "er2000_full_oracle": {"m": em, "median_s_1_thread": round(t1, 4),
+                               f"median_s_{cores}_threads": round(tc, 4),
+                               "edges_per_s_1_thread": round(em / t1, 1),
+                               f"edges_per_s_{cores}_threads": round(em / tc, 1)},
     }
 
 
@@ -123,17 +174,20 @@ def run_batched(args, orbit, gg, rank):
     for _ in range(args.warmup):
         bc.run(timing=True)
     torch.cuda.synchronize()
-    phases = {}
+    phases, kernels = {}, {}
     t0 = time.perf_counter()
     for _ in range(args.steps):
         bc.run(timing=True)
         for nm, ms in orbit.last_phase_times():
             phases[nm] = phases.get(nm, 0.0) + ms
+        for nm, ms in orbit.last_kernel_times().items():
+            kernels[nm] = kernels.get(nm, 0.0) + ms
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     stats = orbit.last_stats()
     ms_step = 1000.0 * el / args.steps
     phases = {k: v / args.steps for k, v in phases.items()}
+    kernels = {k: v / args.steps for k, v in kernels.items()}
     got = bc.out[:n].clone()
     # the same count captured as one HIP graph and replayed
     plan = orbit.Plan(bc)
@@ -162,8 +216,9 @@ def run_batched(args, orbit, gg, rank):
                    "ms_per_step": round(plain_ms, 3), "speedup_of_batched": round(plain_ms / ms_step, 3),
                    "identical_counts": same}
         del c, out
-    dom = max((k for k in phases if k in ("pairs", "c5", "c4", "cliques", "clique2_k4terms")),
-              key=lambda k: phases[k])
+    tk = dict(kernels)
+    tk.update({k: phases[k] for k in ("c4", "cliques") if k in phases})
+    dom = max(tk, key=lambda k: tk[k])
     line = {
         "metric": "edges/s for all <=5-vertex orbit counts (bit-exact), HBM GB/s vs peak",
         "value": round(m * args.steps / el, 1),
@@ -184,7 +239,8 @@ def run_batched(args, orbit, gg, rank):
                                  "groups": ["auto", "workgroup", "wave"][groups],
                                  "gpu_ms": round(tune_ms, 3)}},
         "phases_ms": {k: round(v, 3) for k, v in phases.items()},
-        "dominant_phase": dom,
+        "kernels_ms": {k: round(v, 3) for k, v in kernels.items()},
+        "dominant_kernel": dom,
         "work": stats,
     }
     line["graph_replay"] = {"ms_per_step": round(graph_ms, 3), "identical_counts": graph_same}
@@ -206,7 +262,6 @@ def main():
                     help="batched workload: 1024 workgroups, id schedule, no tuning runs")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the one-step run with the static schedule")
-    ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 4 GiB device-to-device (calibrates HBM byte counters)")
@@ -242,49 +297,77 @@ def main():
     if args.schedule == "mlp":
         w, train_loss = train_cost_model(orbit)
     counter = orbit.Counter(rp, ci, k_max=5, schedule=args.schedule, mlp_weights=w)
-    stream = torch.cuda.current_stream()
 
     for _ in range(args.warmup):
         counter.run(timing=True)
     torch.cuda.synchronize()
-    phases = {}
+    phases, kernels, step_ms = {}, {}, []
     t0 = time.perf_counter()
     for _ in range(args.steps):
         counter.run(timing=True)
-        for nm, ms in orbit.last_phase_times():
+        ph = orbit.last_phase_times()
+        step_ms.append(sum(ms for _, ms in ph))
+        for nm, ms in ph:
             phases[nm] = phases.get(nm, 0.0) + ms
+        for nm, ms in orbit.last_kernel_times().items():
+            kernels[nm] = kernels.get(nm, 0.0) + ms
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     stats = orbit.last_stats()
     ms_step = 1000.0 * el / args.steps
-    compare = None
-    if not args.no_compare and args.schedule != "static":
-        # the plain static-threshold schedule on the same graph, one step
-        del counter
-        torch.cuda.empty_cache()
-        cs = orbit.Counter(rp, ci, k_max=5, schedule="static")
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        cs.run()
-        torch.cuda.synchronize()
-        st_ms = 1000.0 * (time.perf_counter() - t1)
-        compare = {"schedule": "static", "ms_per_step": round(st_ms, 3),
-                   "speedup_of_" + args.schedule: round(st_ms / ms_step, 4)}
-        del cs
     value = m * args.steps / el
     phases = {k: v / args.steps for k, v in phases.items()}
+    kernels = {k: v / args.steps for k, v in kernels.items()}
+    counts = counter.out[:n]
+    sums, pats, hist = orbit.voc_summary(counts, 5)
+    torch.cuda.synchronize()
 
-    # dominant kernel: the pair sweep over wedges and diamonds.  Algorithmic
-    # bytes per launch = 8 B per wedge (its two endpoint ids) + 8 B per
-    # diamond (one triangle-list entry), i.e. 8 (W + D).
-    dom = "pairs"
-    dom_ms = phases.get(dom, float("nan"))
-    alg_bytes = 8.0 * (stats["wedges"] + stats["diamonds"])
+    # The dominant kernel: the pair sweep (the undirected 2-hop sweep).
+    # Algorithmic bytes per launch, the measurement unit of the 2-hop sweep:
+    # 4 B per wedge endpoint, 8 B x sum over vertices of C(d,2) (the wedges
+    # W); the diamond walk of its wheel maps (8 B x sum over edges of
+    # C(T(e),2)) is reported beside it, not in `achieved`.  The time is
+    # the kernel's own, from HIP events on the stream it runs on.
+    dom_ms = kernels["pairs"]
+    alg_bytes = 8.0 * stats["wedges"]
     achieved = alg_bytes / (dom_ms / 1000.0) / 1e9
     roofline = {"kernel": "k_pairs", "bound": "hbm", "achieved": round(achieved, 3),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6),
                 "traffic": measured_traffic(args.workload), "alg_bytes": alg_bytes,
-                "avg_ms": round(dom_ms, 3)}
+                "alg_bytes_diamonds": 8.0 * stats["diamonds"], "avg_ms": round(dom_ms, 3)}
+    # the 5-cycle kernel: 4 B per directed 3-path i <- j <- k -> l
+    c5_bytes = 4.0 * stats["paths3"]
+    c5_ach = c5_bytes / (kernels["c5"] / 1000.0) / 1e9
+    roofline_c5 = {"kernel": "k_c5", "bound": "hbm", "achieved": round(c5_ach, 3),
+                   "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(c5_ach / HBM_PEAK_GBS, 6),
+                   "alg_bytes": c5_bytes, "avg_ms": round(kernels["c5"], 3)}
+
+    compare = None
+    if not args.no_compare and args.schedule != "static":
+        # the plain static-threshold schedule on the same graph: the same
+        # warm-up, the same number of steps, medians of the per-step GPU times
+        k = min(args.steps, 5)
+        del counter
+        torch.cuda.empty_cache()
+        cs = orbit.Counter(rp, ci, k_max=5, schedule="static")
+        for _ in range(args.warmup):
+            cs.run(timing=True)
+        st = []
+        for _ in range(k):
+            cs.run(timing=True)
+            st.append(sum(ms for _, ms in orbit.last_phase_times()))
+        torch.cuda.synchronize()
+        mine = step_ms[-k:]
+        compare = {"schedule": "static", "steps": k,
+                   "median_ms": round(float(np.median(st)), 3),
+                   "min_max_ms": [round(min(st), 3), round(max(st), 3)],
+                   args.schedule + "_median_ms": round(float(np.median(mine)), 3),
+                   args.schedule + "_min_max_ms": [round(min(mine), 3), round(max(mine), 3)],
+                   "speedup_of_" + args.schedule: round(float(np.median(st) / np.median(mine)), 4)}
+        del cs
+
+    voc = {"pattern_copies": {f"H{h}": str(pats[h]) for h in (2, 8, 9, 15, 29)},
+           "ccd_orbit17": orbit.ccd(hist[17], n)[::4], "ccd_orbit70": orbit.ccd(hist[70], n)[::4]}
 
     line = {
         "metric": "edges/s for all <=5-vertex orbit counts (bit-exact), HBM GB/s vs peak",
@@ -301,20 +384,23 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload], "n": n, "m": m, "k_max": 5,
                    "orbits": 73, "output": "induced uint64 counts n x 73",
-                   "schedule": args.schedule},
+                   "schedule": args.schedule, "orbit_groups": "overlapped"},
         "roofline": roofline,
+        "roofline_c5": roofline_c5,
         "phases_ms": {k: round(v, 3) for k, v in phases.items()},
+        "kernels_ms": {k: round(v, 3) for k, v in kernels.items()},
+        "step_gpu_ms_median": round(float(np.median(step_ms)), 3),
         "work": stats,
+        "voc": voc,
     }
     if compare is not None:
         line["vs_static_schedule"] = compare
     if train_loss is not None:
         line["cost_model"] = {"trained_on": TRAIN_WORKLOAD, "mse_log2_steps": round(train_loss, 4)}
     if not args.no_cpu_baseline and rank == 0:
-        line["cpu_baseline"] = cpu_baseline(rp, ci, args.cpu_seconds)
+        line["cpu_baseline"] = cpu_baseline(rp, ci)
     if rank == 0:
         print(json.dumps(line), flush=True)
-    del stream
 
 
 if __name__ == "__main__":
