@@ -78,6 +78,14 @@ extern "C" {
                                degree); the counts come back under the caller's ids.  One
                                graph only (not batched), not with features_out/steps_out;
                                the workspace grows by about 8m + 40n bytes. */
+#define ORB_ASYNC 0x10u      /* orbit_count_ex / orbit_count_edges: enqueue the whole count
+                               on `stream` and return without any host synchronisation,
+                               using the sizes orbit_prepare reported for this graph
+                               (orb_opts.sizes, required); the peeling runs that many
+                               launch groups and stops early on the device.  Sizes
+                               that do not match the graph are detected on the device
+                               and reported, with every other error, by
+                               orbit_count_status.  Not with ORB_TIMING. */
 #define ORB_SERIAL_GROUPS 0x8u /* k_max = 5: run the three independent orbit groups
                                (pair sweep, 5-cycles, second clique pass) one after
                                another on `stream` instead of overlapping them on two
@@ -100,6 +108,18 @@ extern "C" {
 #define ORB_GROUPS_WAVE 2u  /* a 64-lane wave per source, four sources per workgroup,
                                queue entries taken 16 at a time */
 
+/* Data-dependent sizes of one graph's count, as orbit_prepare finds them:
+ * the number of 32-round peeling launch groups, the triangle count, the
+ * largest peel level (degeneracy - the out-degree bound) and, for batches,
+ * the largest graph. */
+typedef struct orb_sizes {
+    uint64_t ntri;
+    uint32_t peel_groups;
+    uint32_t maxlevel;
+    uint32_t gmax;
+    uint32_t reserved;
+} orb_sizes;
+
 /* cost model: a 3 -> 32 -> 32 -> 1 fp32 ReLU network, parameters packed as
  * W1[32][3], b1[32], W2[32][32], b2[32], W3[32], b3 */
 #define ORB_MLP_PARAMS 1217
@@ -121,6 +141,7 @@ typedef struct orb_opts {
                                   cycles summed over execution groups in the pair sweep's
                                   passes: wedges, wheel maps, pair terms, centre terms;
                                   accumulated (the caller zeroes them) */
+    const orb_sizes *sizes;   /* host, needed by ORB_ASYNC: from orbit_prepare */
 } orb_opts;
 
 /* Number of output columns K for k_max (3, 4 or 5); 0 if k_max is invalid. */
@@ -191,6 +212,20 @@ int orbit_count_noalloc(const uint32_t *row_ptr, const uint32_t *col_idx, uint32
 
 /* Size in bytes of orbit_count_noalloc's static buffer (host only). */
 uint64_t orbit_noalloc_capacity(void);
+
+/* Validates the graph and finds the sizes its count depends on (this call
+ * synchronises `stream`), for asynchronous counts (ORB_ASYNC): writes the
+ * workspace size orbit_count_ex needs with these opts to *bytes and the
+ * sizes to *sizes.  Allocates and frees a temporary workspace like
+ * orbit_workspace_query. */
+int orbit_prepare(const uint32_t *row_ptr, const uint32_t *col_idx, uint32_t n, uint64_t m,
+                  int k_max, void *stream, const orb_opts *opts, uint64_t *bytes,
+                  orb_sizes *sizes);
+
+/* Status of the last count enqueued on `workspace` (one graph; the device
+ * state is at its start): waits for `stream`, then returns ORB_OK or the
+ * error the kernels recorded -- the status call of ORB_ASYNC counts. */
+int orbit_count_status(const void *workspace, void *stream);
 
 /* Workspace size that orbit_count_ex needs for this graph.  The size
  * depends on the number of triangles, so this call validates the graph,

@@ -61,8 +61,11 @@ __global__ void k_tri_fill(const u32 *src, const u64 *out_ptr, const u32 *out_nb
 // Per-slot triangle counts: T = all triangles on the edge, Tin = those
 // whose third vertex precedes both ends (|N-(x) & N-(y)|), Tmid (on the
 // slots of arc a->c) = those whose third vertex lies between (|N+(a) & N-(c)|).
+// The kernels that read triangle records or lists do nothing once an error
+// is recorded: after a size check failed the records were never written.
 __global__ void k_tri_slots(const u32 *rev, u64 ntri, const u32 *tri_sab, const u32 *tri_sac,
-                            const u32 *tri_sbc, u32 *T, u32 *Tin, u32 *Tmid) {
+                            const u32 *tri_sbc, u32 *T, u32 *Tin, u32 *Tmid, const DevState *st) {
+    if (st->err) return;
     for (u64 t = GTID; t < ntri; t += GSTRIDE) {
         u32 sab = tri_sab[t], sac = tri_sac[t], sbc = tri_sbc[t];
         atomicAdd(&T[sab], 1u); atomicAdd(&T[rev[sab]], 1u);
@@ -88,7 +91,8 @@ __device__ inline void tl_push(u32 s_xy, u32 s_xz, u32 s_yz, const u32 *src, con
 
 __global__ void k_tl_fill(const u32 *src, const u32 *ci, const u32 *rev, u64 ntri,
                           const u32 *tri_sab, const u32 *tri_sac, const u32 *tri_sbc,
-                          const u64 *tl_ptr, u32 *tl_cur, uint2 *tl) {
+                          const u64 *tl_ptr, u32 *tl_cur, uint2 *tl, const DevState *st) {
+    if (st->err) return;
     for (u64 t = GTID; t < ntri; t += GSTRIDE) {
         u32 sab = tri_sab[t], sac = tri_sac[t], sbc = tri_sbc[t];
         u32 sba = rev[sab], sca = rev[sac], scb = rev[sbc];
@@ -247,7 +251,8 @@ __device__ inline TLView tl_view(u32 s, const u32 *src, const u32 *ci, const u32
 // E9<u,v> = sum over triangles (u,v,x) of (T(u,x) - 1)   [at slot (u,v)].
 __global__ void k_edge_e7e9(const u32 *src, const u32 *ci, const u32 *rev, const u32 *deg,
                             const u32 *T, const u64 *tl_ptr, const uint2 *tl, u64 M2, u64 *E7,
-                            u64 *E9) {
+                            u64 *E9, const DevState *st) {
+    if (st->err) return;
     for (u64 s = GTID; s < M2; s += GSTRIDE) {
         TLView v = tl_view((u32)s, src, ci, rev, T, tl_ptr, tl);
         u64 e7 = 0, e9 = 0;
@@ -667,7 +672,8 @@ __global__ void __launch_bounds__(WG) k_clique(int pass, u32 n, const u32 *rev,
 // by the triangle that the 4-clique shares with u).
 __global__ void k_tri_k4terms(const u32 *src, const u32 *ci, const u32 *T, u64 ntri,
                               const u32 *tri_c, const u32 *tri_sab, const u32 *tri_sac,
-                              const u32 *tri_sbc, const u32 *K4t, u64 *ni) {
+                              const u32 *tri_sbc, const u32 *K4t, u64 *ni, const DevState *st) {
+    if (st->err) return;
     for (u64 r = GTID; r < ntri; r += GSTRIDE) {
         u64 kt = K4t[r];
         if (!kt) continue;

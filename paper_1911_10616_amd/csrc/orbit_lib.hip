@@ -568,12 +568,23 @@ int count_impl(const u32 *rp, const u32 *ci, u32 n, u64 m, const u64 *vptr, u32 
                u64 *counts, unsigned char *ovf, u64 *edge_out, void *ws,
                u64 ws_bytes, u64 *ws_required, hipStream_t s, const orb_opts *opts,
                bool query_only, Plan *pl = nullptr, u32 *nwg_fit = nullptr) {
-    const bool cap = pl && pl->capture;
     const u32 flags = opts ? opts->flags : 0u;
     const int K = orbit_num_orbits(k_max);
     if (!K) return ORB_E_INVALID_ARG;
-    if (flags & ~(ORB_NONINDUCED | ORB_TIMING | ORB_RELABEL | ORB_SERIAL_GROUPS))
+    if (flags & ~(ORB_NONINDUCED | ORB_TIMING | ORB_RELABEL | ORB_SERIAL_GROUPS | ORB_ASYNC))
         return ORB_E_INVALID_ARG;
+    Plan async_plan;
+    if (flags & ORB_ASYNC) {  // the sizes of orbit_prepare; no host read back
+        if (pl || query_only || !opts->sizes || (flags & ORB_TIMING)) return ORB_E_INVALID_ARG;
+        async_plan.capture = true;
+        async_plan.peel_groups = (int)opts->sizes->peel_groups;
+        async_plan.ntri = opts->sizes->ntri;
+        async_plan.maxlevel = opts->sizes->maxlevel;
+        async_plan.gmax = opts->sizes->gmax;
+        if (async_plan.peel_groups < 1 && n) return ORB_E_INVALID_ARG;
+        pl = &async_plan;
+    }
+    const bool cap = pl && pl->capture;  // nothing is read back to the host
     const bool relabel = (flags & ORB_RELABEL) != 0;
     if (relabel && (vptr || opts->features_out || opts->steps_out)) return ORB_E_INVALID_ARG;
     if (edge_out && (relabel || vptr || k_max < 4)) return ORB_E_INVALID_ARG;
@@ -717,7 +728,7 @@ int count_impl(const u32 *rp, const u32 *ci, u32 n, u64 m, const u64 *vptr, u32 
         k_tri_fill<<<grid_for(m, WG), WG, 0, s>>>(src, outptr, outnbr, outslot, m, triptr, tri_c,
                                                   tri_sab, tri_sac, tri_sbc, st);
         k_tri_slots<<<grid_for(ntri, WG), WG, 0, s>>>(rev, ntri, tri_sab, tri_sac, tri_sbc, T, Tin,
-                                                      Tmid);
+                                                      Tmid, st);
         HCHK(hipGetLastError());
     }
     tm.mark("triangles");
@@ -726,8 +737,8 @@ int count_impl(const u32 *rp, const u32 *ci, u32 n, u64 m, const u64 *vptr, u32 
         int rc2 = scan<u32>(tllen, M2, tlptr, bsum, st, s);
         if (rc2) return rc2;
         k_tl_fill<<<grid_for(ntri, WG), WG, 0, s>>>(src, ci, rev, ntri, tri_sab, tri_sac, tri_sbc,
-                                                    tlptr, tlcur, tl);
-        k_edge_e7e9<<<grid_for(M2, WG), WG, 0, s>>>(src, ci, rev, deg, T, tlptr, tl, M2, E7, E9);
+                                                    tlptr, tlcur, tl, st);
+        k_edge_e7e9<<<grid_for(M2, WG), WG, 0, s>>>(src, ci, rev, deg, T, tlptr, tl, M2, E7, E9, st);
         HCHK(hipGetLastError());
         if (k_max >= 5) {
             // lists sorted by third vertex for the pair sweep; the queue of
@@ -803,7 +814,7 @@ int count_impl(const u32 *rp, const u32 *ci, u32 n, u64 m, const u64 *vptr, u32 
                                           tri_sbc, scr_clq, L.stride_clq, dmax, clq_d, work + wi++, order, K4t, K4v, K4e,
                                           ni, st));
             k_tri_k4terms<<<grid_for(ntri, WG), WG, 0, sc>>>(src, ci, T, ntri, tri_c, tri_sab,
-                                                             tri_sac, tri_sbc, K4t, ni);
+                                                             tri_sac, tri_sbc, K4t, ni, st);
             HCHK(hipGetLastError());
         }
         tm.kend(2, sc);
@@ -913,6 +924,39 @@ int orbit_count_ex(const uint32_t *row_ptr, const uint32_t *col_idx, uint32_t n,
                    const orb_opts *opts) {
     return count_impl(row_ptr, col_idx, n, m, nullptr, 0, k_max, (u64 *)counts, overflow_flags,
                       nullptr, workspace, ws_bytes, (u64 *)ws_required, (hipStream_t)stream, opts, false);
+}
+
+int orbit_prepare(const uint32_t *row_ptr, const uint32_t *col_idx, uint32_t n, uint64_t m,
+                  int k_max, void *stream, const orb_opts *opts, uint64_t *bytes,
+                  orb_sizes *sizes) {
+    if (!bytes || !sizes || !orbit_num_orbits(k_max)) return ORB_E_INVALID_ARG;
+    if (2 * m >= (1ull << 32)) return ORB_E_INVALID_ARG;
+    if (opts && (opts->flags & ORB_ASYNC)) return ORB_E_INVALID_ARG;
+    Layout L;
+    layout_phase1(L, n, m, wants_relabel(opts));
+    void *tmp = nullptr;
+    if (hipMalloc(&tmp, L.p1_end) != hipSuccess) return ORB_E_DEVICE;
+    u64 req = 0;
+    Plan pl;
+    int rc = count_impl(row_ptr, col_idx, n, m, nullptr, 0, k_max, nullptr, nullptr, nullptr, tmp,
+                        L.p1_end, &req, (hipStream_t)stream, opts, true, &pl);
+    (void)hipFree(tmp);
+    if (rc) return rc;
+    *bytes = req;
+    sizes->ntri = pl.ntri;
+    sizes->peel_groups = (uint32_t)pl.peel_groups;
+    sizes->maxlevel = pl.maxlevel;
+    sizes->gmax = pl.gmax;
+    sizes->reserved = 0;
+    return ORB_OK;
+}
+
+int orbit_count_status(const void *workspace, void *stream) {
+    if (!workspace) return ORB_E_INVALID_ARG;
+    DevState h;
+    int rc = read_state((DevState *)workspace, &h, (hipStream_t)stream);
+    if (rc) return rc;
+    return h.err ? err_to_status(h.err) : ORB_OK;
 }
 
 int orbit_count_edges(const uint32_t *row_ptr, const uint32_t *col_idx, uint32_t n, uint64_t m,

@@ -19,6 +19,7 @@ ORB_NONINDUCED = 0x1
 ORB_TIMING = 0x2
 ORB_RELABEL = 0x4
 ORB_SERIAL_GROUPS = 0x8
+ORB_ASYNC = 0x10
 SCHED_ID, SCHED_STATIC, SCHED_MLP = 0, 1, 2
 SCHEDULES = {"id": SCHED_ID, "static": SCHED_STATIC, "mlp": SCHED_MLP}
 GROUPS = {"auto": 0, "wg": 1, "wave": 2}
@@ -30,7 +31,8 @@ EXPORTS = ("orbit_num_orbits", "orbit_count", "orbit_workspace_query", "orbit_co
            "orbit_workspace_query_batched", "orbit_autotune", "orbit_plan_create",
            "orbit_plan_launch", "orbit_plan_status", "orbit_plan_destroy",
            "orbit_count_noalloc", "orbit_noalloc_capacity", "orbit_count_edges",
-           "orbit_num_patterns", "orbit_voc_summary", "orbit_last_kernel_times")
+           "orbit_num_patterns", "orbit_voc_summary", "orbit_last_kernel_times",
+           "orbit_prepare", "orbit_count_status")
 
 
 class OrbError(RuntimeError):
@@ -43,7 +45,14 @@ class _Opts(ctypes.Structure):
     _fields_ = [("flags", ctypes.c_uint32), ("num_wg", ctypes.c_uint32),
                 ("schedule", ctypes.c_uint32), ("groups", ctypes.c_uint32),
                 ("mlp_weights", ctypes.c_void_p), ("features_out", ctypes.c_void_p),
-                ("steps_out", ctypes.c_void_p), ("pass_cycles_out", ctypes.c_void_p)]
+                ("steps_out", ctypes.c_void_p), ("pass_cycles_out", ctypes.c_void_p),
+                ("sizes", ctypes.c_void_p)]
+
+
+class _Sizes(ctypes.Structure):
+    _fields_ = [("ntri", ctypes.c_uint64), ("peel_groups", ctypes.c_uint32),
+                ("maxlevel", ctypes.c_uint32), ("gmax", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
 
 
 def _load(path=LIB):
@@ -103,6 +112,11 @@ def _load(path=LIB):
     lib.orbit_count_edges.argtypes = [vp, vp, u32, u64, ctypes.c_int, vp, vp, vp, u64,
                                       ctypes.POINTER(u64), vp, ctypes.POINTER(_Opts)]
     lib.orbit_count_edges.restype = ctypes.c_int
+    lib.orbit_prepare.argtypes = [vp, vp, u32, u64, ctypes.c_int, vp, ctypes.POINTER(_Opts),
+                                  ctypes.POINTER(u64), ctypes.POINTER(_Sizes)]
+    lib.orbit_prepare.restype = ctypes.c_int
+    lib.orbit_count_status.argtypes = [vp, vp]
+    lib.orbit_count_status.restype = ctypes.c_int
     lib.orbit_num_patterns.argtypes = [ctypes.c_int]
     lib.orbit_num_patterns.restype = ctypes.c_int
     lib.orbit_voc_summary.argtypes = [vp, u32, ctypes.c_int, vp, vp, vp, vp]
@@ -195,7 +209,8 @@ class Counter:
 
     def __init__(self, row_ptr, col_idx, k_max=5, noninduced=False, num_wg=0, stream=None,
                  schedule="id", mlp_weights=None, features_out=None, steps_out=None,
-                 groups="auto", pass_cycles_out=None, relabel=False, serial=False):
+                 groups="auto", pass_cycles_out=None, relabel=False, serial=False,
+                 asynchronous=False):
         """schedule: "id", "static" or "mlp" (source order of the per-source
         kernels; needs mlp_weights, a float32 device tensor of MLP_PARAMS
         values, for "mlp").  features_out (float32 [n, 3]) and steps_out
@@ -219,10 +234,32 @@ class Counter:
         self.opts = _opts(noninduced, False, num_wg, **extra)
         self.topts = _opts(noninduced, True, num_wg, **extra)
         self.stream = stream
-        self.ws_bytes = workspace_bytes(self.rp, self.ci, k_max, noninduced, num_wg, stream,
-                                        groups=groups, relabel=relabel)
+        self.sizes = None
+        if asynchronous:
+            # orbit_prepare: the sizes of this graph's count (synchronises
+            # once); run() then enqueues with no host synchronisation
+            self.sizes = _Sizes()
+            need = ctypes.c_uint64(0)
+            _check(_lib.orbit_prepare(ctypes.c_void_p(self.rp.data_ptr()),
+                                      ctypes.c_void_p(self.ci.data_ptr()), self.n, self.m, k_max,
+                                      _stream_ptr(stream), ctypes.byref(self.opts),
+                                      ctypes.byref(need), ctypes.byref(self.sizes)),
+                   "orbit_prepare")
+            self.ws_bytes = int(need.value)
+            for o in (self.opts, self.topts):
+                o.flags |= ORB_ASYNC
+                o.sizes = ctypes.cast(ctypes.pointer(self.sizes), ctypes.c_void_p)
+        else:
+            self.ws_bytes = workspace_bytes(self.rp, self.ci, k_max, noninduced, num_wg, stream,
+                                            groups=groups, relabel=relabel)
         self.ws = torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8, device=self.rp.device)
         self.out = torch.empty((max(self.n, 1), self.K), dtype=torch.int64, device=self.rp.device)
+
+    def status(self):
+        """orbit_count_status: waits for the stream and raises if the last
+        count recorded an error (the check of asynchronous counts)."""
+        _check(_lib.orbit_count_status(ctypes.c_void_p(self.ws.data_ptr()),
+                                       _stream_ptr(self.stream)), "orbit_count_status")
 
     def run(self, timing=False, overflow_flags=None):
         """Counts into self.out; overflow_flags: optional uint8 device tensor
