@@ -24,7 +24,12 @@ import pytest
 import oracle
 from paper_1911_10616_amd import graphgen as gg
 
-pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+# One count of this graph takes minutes in a single library call, during
+# which a captured test run prints nothing; it runs when asked for:
+#   ORBIT_RMAT22=1 python -u -m pytest tests/test_gpu_rmat22.py -s
+pytestmark = [pytest.mark.gpu, pytest.mark.slow,
+              pytest.mark.skipif(os.environ.get("ORBIT_RMAT22") != "1",
+                                 reason="minutes-long full-size R-MAT 22 count: set ORBIT_RMAT22=1")]
 U = np.uint64
 M64 = 1 << 64
 
