@@ -3,9 +3,10 @@
 Two builds of the same sources:
 * ``liborbit_hip.so`` -- the library;
 * ``liborbit_hip_tiles.so`` -- the same code with every LDS tile shrunk
-  (clique bit rows, pair-sweep wheel maps, the long triangle-list sort), so that graphs small enough for the CPU oracle take
-  the paths that only hubs of large graphs take in the library build.  Only
-  the tests load it.
+  (clique bit rows, pair-sweep wheel maps, the long triangle-list sort) and
+  the per-source maps kept in HBM, so that graphs small enough for the CPU
+  oracle take the paths that only hubs and large graphs take in the library
+  build.  Only the tests load it.
 """
 from __future__ import annotations
 
@@ -19,8 +20,8 @@ LIB_TILES = os.path.join(HERE, "liborbit_hip_tiles.so")
 SOURCES = ["orbit_lib.hip", "orbit_prep.hip", "orbit_count.hip", "orbit_combine.hip",
            "orbit_sched.hip", "orbit_common.h", "orbit_tables.h"]
 # tile sizes of the test build (each the smallest its kernel accepts or a
-# size a 40..120-vertex graph exceeds)
-SMALL_TILES = {"CLQ_LDS_D": 16, "PAIR_KMAP_LDS": 16, "TL_SORT_LDS": 128}
+# size a 40..120-vertex graph exceeds; no per-source maps in LDS)
+SMALL_TILES = {"CLQ_LDS_D": 16, "PAIR_KMAP_LDS": 16, "TL_SORT_LDS": 128, "LDS_MAP_BUDGET": 0}
 
 
 def hipcc_command(out: str = LIB, defines=None):

@@ -307,25 +307,26 @@ struct GpWave {
 // takes GP::chunk consecutive entries per atomic on the shared counter (light
 // sources would otherwise serialise on it).  q[0..1] = the group's current
 // range of queue entries, q[2] = the source handed out; both start at 0.
-// Once an error is recorded (st->err) the queue reads as empty, so a
-// replayed plan whose sizes no longer match its buffers stops early.
+// Once an error is recorded (st->err) the queue reads as empty from the next
+// chunk on, so a replayed plan whose sizes no longer match its buffers stops
+// early.
 template <class GP>
 __device__ inline u32 next_source(u32 *counter, u32 *q, const u32 *order, u32 n,
                                   const DevState *st) {
     GP::sync();
     if (GP::rank() == 0) {
-        if (__atomic_load_n(&st->err, __ATOMIC_RELAXED)) {
-            q[2] = n;
-        } else {
-            if (q[0] >= q[1]) {
-                const u32 i = atomicAdd(counter, GP::chunk);
-                q[0] = i;
-                q[1] = i < n ? (n - i < GP::chunk ? n : i + GP::chunk) : i;
-            }
-            const u32 i = q[0];
-            q[2] = i < q[1] ? (order ? order[i] : i) : n;
-            q[0] = i + 1;
+        if (q[0] >= q[1]) {
+            // the error word is looked at once per chunk (an agent-scope
+            // load: it stays in the L2)
+            const bool stop =
+                __hip_atomic_load(&st->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+            const u32 i = stop ? n : atomicAdd(counter, GP::chunk);
+            q[0] = i;
+            q[1] = i < n ? (n - i < GP::chunk ? n : i + GP::chunk) : i;
         }
+        const u32 i = q[0];
+        q[2] = i < q[1] ? (order ? order[i] : i) : n;
+        q[0] = i + 1;
     }
     GP::sync();
     return q[2];
@@ -354,16 +355,38 @@ __device__ inline u64 block_sum_u64(u64 v, u64 *sh) {
     return t;
 }
 
+// ---- Per-source maps in LDS.  When a map (indexed by vertex within the
+// source's graph) is small -- small graphs, and every graph of a batch of
+// small graphs -- each wave of a wave-group kernel keeps its maps in its own
+// slice of the workgroup's dynamic LDS (lmw u64 words per wave) instead of
+// the per-group scratch in HBM.  The slices are cleared once when the
+// workgroup starts; after that each source restores what it dirtied, as in
+// HBM.  The pointers are formed from the LDS array by plain pointer
+// arithmetic so that the compiler emits LDS instructions for them.
+__device__ inline u64 *wave_lds_slice(u64 *dyn, u64 lmw) {
+    return dyn + (u64)wave_in_wg() * lmw;
+}
+__device__ inline void clear_lds(u64 *p, u64 words) {
+    for (u64 i = threadIdx.x; i < words; i += WG) p[i] = 0;
+    __syncthreads();
+}
+// map entries rounded up so that the arrays after them stay 8-byte aligned
+__host__ __device__ inline u32 map_even(u32 mapn) { return (mapn + 1) & ~1u; }
+// u64 words per wave of each kernel's maps
+__host__ __device__ inline u64 c4_lds_words(u32 mapn) { return map_even(mapn); }
+__host__ __device__ inline u64 pair_lds_words(u32 mapn) { return 2ull * mapn + map_even(mapn) / 2; }
+
 // ---- 4-cycles (Chiba-Nishizeki).  For every top vertex x: the wedges
 // x - y - z with y and z before x in rank order; cnt[z] = number of such y.
 // Every 4-cycle has a unique top x and opposite z; it adds C(cnt,2) to x and
 // z, cnt-1 to each middle y, and cnt-1 to the edges (x,y) and (y,z).
 // Gives C4(u) (orbit 8) and C4(e) (edge orbit E5).
-template <class GP>
+// LM: the maps (cnt, touched) live in LDS (lmw words per wave).
+template <class GP, bool LM>
 __global__ void __launch_bounds__(WG) k_c4(const u32 *rp, const u32 *ci, const u32 *rev,
                                           const u64 *key, u32 n, unsigned char *scratch,
                                           u64 stride, u32 *work, const u32 *order, u32 mapn,
-                                          const u32 *gbase, u64 *C4v, u64 *C4e,
+                                          const u32 *gbase, u64 lmw, u64 *C4v, u64 *C4e,
                                           const DevState *st) {
     __shared__ u32 sh_q_[GP::per_wg][3], sh_nt_[GP::per_wg], sh_next_[GP::per_wg];
     u32 *sh_q = sh_q_[GP::id()];
@@ -371,9 +394,18 @@ __global__ void __launch_bounds__(WG) k_c4(const u32 *rp, const u32 *ci, const u
     u32 &sh_nt = sh_nt_[GP::id()];
     u32 &sh_next = sh_next_[GP::id()];
     __shared__ u64 sh_red[WAVES_PER_WG];
-    unsigned char *base = scratch + GP::global_id() * stride;
-    u32 *cnt = (u32 *)base;
-    u32 *touched = (u32 *)align256((unsigned char *)(cnt + mapn));
+    static_assert(!LM || GP::per_wg > 1, "LDS maps are per wave");
+    extern __shared__ u64 dyn_lds[];
+    u32 *cnt, *touched;
+    if constexpr (LM) {
+        clear_lds(dyn_lds, WAVES_PER_WG * lmw);
+        cnt = (u32 *)wave_lds_slice(dyn_lds, lmw);
+        touched = cnt + map_even(mapn);
+    } else {
+        unsigned char *base = scratch + GP::global_id() * stride;
+        cnt = (u32 *)base;
+        touched = (u32 *)align256((unsigned char *)(cnt + mapn));
+    }
     for (;;) {
         u32 x = next_source<GP>(work, sh_q, order, n, st);
         if (x >= n) break;
@@ -836,15 +868,18 @@ __device__ inline void flat_walk(FlatLds &L, u32 n_mine, F f) {
     wave_sync();
 }
 
-template <class GP>
+// LM: the pair state (sta, e2, touched) lives in LDS, lmw words per wave
+// after the wheel maps (then every arc's wheel map is an LDS one).
+template <class GP, bool LM>
 __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, const u32 *src,
                                              const u32 *rev, const u32 *deg, const u32 *T,
                                              const u64 *tl_ptr, const uint2 *tl, u32 n,
                                              unsigned char *scratch, u64 stride, u32 *work,
                                              const u32 *order, u32 mapn, const u32 *gbase,
-                                             u32 kl, u64 *steps, u64 *pass_cycles, u64 *Q,
-                                             u64 *vacc, const DevState *st) {
+                                             u32 kl, u64 lmw, u64 *steps, u64 *pass_cycles,
+                                             u64 *Q, u64 *vacc, const DevState *st) {
     constexpr bool kWaveGroups = GP::per_wg > 1;
+    static_assert(!LM || kWaveGroups, "LDS maps are per wave");
     __shared__ u32 sh_q_[GP::per_wg][3], sh_nt_[GP::per_wg], sh_next_[GP::per_wg];
     u32 *sh_q = sh_q_[GP::id()];
     if (GP::rank() == 0) { sh_q[0] = 0; sh_q[1] = 0; }
@@ -863,9 +898,25 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
     unsigned short *l_tk0 = (unsigned short *)(l_k0 + WAVES_PER_WG * kl);
     u32 *hmap = l_k0;
     const u32 hmax = 6 * kl;
-    PairState P = pair_state(scratch + GP::global_id() * stride, mapn, kWaveGroups);
-    u32 *Kw = kWaveGroups ? P.K + (u64)wave_in_wg() * mapn : nullptr;
-    u32 *tkw = kWaveGroups ? P.tk + (u64)wave_in_wg() * mapn : nullptr;
+    PairState P;
+    u32 *Kw = nullptr, *tkw = nullptr;
+    if constexpr (LM) {
+        if (mapn > kl) {  // the launch must give every arc an LDS wheel map
+            if (threadIdx.x == 0) atomicOr((u32 *)&st->err, ERRB_INTERNAL);
+            return;
+        }
+        u64 *maps = dyn_lds + 3ull * kl;  // after the wheel maps (24 kl bytes)
+        clear_lds(maps, WAVES_PER_WG * lmw);
+        P.sta = wave_lds_slice(maps, lmw);
+        P.e2 = P.sta + mapn;
+        P.ext = P.e2;  // wide sources cannot occur in maps this small
+        P.touched = (u32 *)(P.e2 + mapn);
+        P.K = P.tk = nullptr;
+    } else {
+        P = pair_state(scratch + GP::global_id() * stride, mapn, kWaveGroups);
+        Kw = kWaveGroups ? P.K + (u64)wave_in_wg() * mapn : nullptr;
+        tkw = kWaveGroups ? P.tk + (u64)wave_in_wg() * mapn : nullptr;
+    }
     const u32 lane = lane_id();
     // every thread of the workgroup clears its share, then all wait (the
     // slices belong to different waves)
@@ -879,7 +930,7 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
         const u32 ba = rp[a], da = rp[a + 1] - ba;
         if (da < 2) continue;
         const u64 dega = da;
-        const bool wide = da >= PS_WIDE_DEG;
+        const bool wide = !LM && da >= PS_WIDE_DEG;
         u64 nsteps = 0;  // loop iterations of this thread for this source
         u64 t_pass = 0;  // clock at the last pass boundary (profiling)
         for (u32 i = GP::rank(); i < da; i += GP::size) P.sta[ci[ba + i] - vb] = PS_ADJ;
@@ -947,7 +998,7 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
             const u32 say = ba + iy, y = ci[say];
             if (T[say] == 0) return;
             const u32 by = rp[y], dy = rp[y + 1] - by;
-            const bool inl = dy <= kl;
+            const bool inl = LM || dy <= kl;  // with LM, dy < mapn <= kl (checked at the start)
             if (!inl && !kWaveGroups) return;  // a hub arc: the whole group, below
             u32 *kc = inl ? l_k0 + wave_in_wg() * kl : Kw;
             unsigned short *tl_l = l_tk0 + wave_in_wg() * kl;
@@ -1185,7 +1236,7 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
         if (pass_cycles) pass_mark(pass_cycles, 4, t_pass);
         if (steps) {  // per-source work, the training target of the scheduler
             u64 tot = GP::sum(nsteps, sh_red);
-            if (GP::rank() == 0) steps[a] += tot;
+            if (GP::rank() == 0) atomic_add_u64(&steps[a], tot);  // the 5-cycle kernel may run alongside
         }
         GP::sync();
     }
@@ -1384,7 +1435,7 @@ __global__ void __launch_bounds__(WG) k_c5(const u32 *rp, const u32 *ci, const u
         if (GP::rank() == 0) atomic_add_u64(&cacc[l], accl);
         if (steps) {
             const u64 tot = GP::sum(nsteps, sh_red);
-            if (GP::rank() == 0) steps[l] += tot;
+            if (GP::rank() == 0) atomic_add_u64(&steps[l], tot);  // the pair sweep may run alongside
         }
         GP::sync();
         // reset: P, CI of the 3-path ends; C, TO, SW of the middle vertices;

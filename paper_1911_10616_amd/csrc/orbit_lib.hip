@@ -24,6 +24,13 @@ const int kMaxPhases = 24;
 const u32 kWaveGroupMaxMap = 4096;
 const u32 kWaveGroupMaxOut = 64;
 const u64 kMaxDynLds = 156 << 10;  // dynamic LDS per workgroup (160 KB per workgroup on gfx950)
+// Per-source maps go to LDS (wave groups) when a workgroup's four slices and
+// the kernel's other dynamic LDS fit in this many bytes: two workgroups per
+// compute unit still fit in its 160 KB.
+#ifndef LDS_MAP_BUDGET
+#define LDS_MAP_BUDGET (76u << 10)
+#endif
+const u64 kLdsMapBudget = LDS_MAP_BUDGET;
 const u32 kRelabelSortWg = 64;     // workgroups sorting the long rows of a relabelled CSR
 thread_local float g_phase_ms[kMaxPhases];
 thread_local const char *g_phase_name[kMaxPhases];
@@ -676,6 +683,15 @@ int count_impl(const u32 *rp, const u32 *ci, u32 n, u64 m, const u64 *vptr, u32 
     const size_t pair_lds = (size_t)WAVES_PER_WG * pair_kl * 6;
     const u32 c5_wg = L.nwg_c5;
     const u32 grp = L.nwg * L.per_wg, grp5 = c5_wg * L.per_wg;  // scratch rows in use
+    // per-source maps in LDS (small maps, wave groups).  The 5-cycle kernel
+    // keeps its maps in HBM: with them in LDS (49 bytes per vertex and
+    // wave) it ran slower on the 100k-graph batch, two workgroups per
+    // compute unit being too few for its chains of dependent loads.
+    const u64 c4_lmw = c4_lds_words(mapn), pair_lmw = pair_lds_words(mapn);
+    const u64 slices = 8ull * WAVES_PER_WG;
+    const bool lm_c4 = wave_groups && slices * c4_lmw <= kLdsMapBudget;
+    const bool lm_pairs = wave_groups && mapn <= pair_kl &&
+                          pair_lds + slices * pair_lmw <= kLdsMapBudget;
 
     // zero the accumulators (the contiguous phase-2 region up to ni) and
     // the per-source scratch
@@ -759,11 +775,19 @@ int count_impl(const u32 *rp, const u32 *ci, u32 n, u64 m, const u64 *vptr, u32 
     u32 *work = st->work;
     int wi = 0;
     if (k_max >= 4) {
-        rc = zero_scratch(0, mapn, scratch, L.stride, L, grp, s);
-        if (rc) return rc;
+        if (!lm_c4) {
+            rc = zero_scratch(0, mapn, scratch, L.stride, L, grp, s);
+            if (rc) return rc;
+        }
         tm.mark("zero_c4");
-        WITH_GP(wave_groups, k_c4<GPT><<<L.nwg, WG, 0, s>>>(rp, ci, rev, key, n, scratch, L.stride, work + wi++, order,
-                                  mapn, gbase, C4v, C4e, st));
+        if (lm_c4)
+            k_c4<GpWave, true><<<L.nwg, WG, slices * c4_lmw, s>>>(
+                rp, ci, rev, key, n, scratch, L.stride, work + wi++, order, mapn, gbase, c4_lmw,
+                C4v, C4e, st);
+        else
+            WITH_GP(wave_groups, k_c4<GPT, false><<<L.nwg, WG, 0, s>>>(
+                                     rp, ci, rev, key, n, scratch, L.stride, work + wi++, order,
+                                     mapn, gbase, 0, C4v, C4e, st));
         HCHK(hipGetLastError());
         tm.mark("c4");
         if (ntri) {
@@ -819,13 +843,22 @@ int count_impl(const u32 *rp, const u32 *ci, u32 n, u64 m, const u64 *vptr, u32 
         }
         tm.kend(2, sc);
         if (!conc) tm.mark("clique2_k4terms");
-        rc = zero_scratch(1, mapn, scratch, L.stride, L, grp, s);
-        if (rc) return rc;
+        if (!lm_pairs) {
+            rc = zero_scratch(1, mapn, scratch, L.stride, L, grp, s);
+            if (rc) return rc;
+        }
         if (!conc) tm.mark("zero_pairs");
         tm.kbegin(0, s);
-        WITH_GP(wave_groups, k_pairs<GPT><<<L.nwg, WG, pair_lds, s>>>(rp, ci, src, rev, deg, T, tlptr, tl, n, scratch, L.stride,
-                                     work + wi++, order, mapn, gbase, pair_kl, steps_out,
-                                     opts ? (u64 *)opts->pass_cycles_out : nullptr, Q, vacc, st));
+        u64 *pcyc = opts ? (u64 *)opts->pass_cycles_out : nullptr;
+        if (lm_pairs)
+            k_pairs<GpWave, true><<<L.nwg, WG, pair_lds + slices * pair_lmw, s>>>(
+                rp, ci, src, rev, deg, T, tlptr, tl, n, scratch, L.stride, work + wi++, order,
+                mapn, gbase, pair_kl, pair_lmw, steps_out, pcyc, Q, vacc, st);
+        else
+            WITH_GP(wave_groups, k_pairs<GPT, false><<<L.nwg, WG, pair_lds, s>>>(
+                                     rp, ci, src, rev, deg, T, tlptr, tl, n, scratch, L.stride,
+                                     work + wi++, order, mapn, gbase, pair_kl, 0, steps_out,
+                                     pcyc, Q, vacc, st));
         HCHK(hipGetLastError());
         tm.kend(0, s);
         if (!conc) tm.mark("pairs");
