@@ -112,7 +112,7 @@ void layout_phase1(Layout &L, u32 n, u64 m, bool relabel = false) {
     L.p1_end = c;
 }
 
-// pair sweep: sta, e2, ext (u64), touched (u32); wave groups add the
+// pair sweep: (sta, e2) records (16 bytes), ext (u64), touched (u32); wave groups add the
 // per-wave global wheel maps and their touched lists (u32, 4 x n each)
 u64 pair_stride(u32 n, bool wave_maps) {
     return 3 * align_up(8ull * n, 256) + align_up(4ull * n, 256) +
@@ -238,7 +238,7 @@ int zero_ranges(int which, u32 n, bool wave_maps, ZeroRange *r) {
         r[0] = {0, a4};
         return 1;
     }
-    if (which == 1) {  // pair sweep: sta, e2, ext ... then the wave maps K
+    if (which == 1) {  // pair sweep: records, ext ... then the wave maps K
         r[0] = {0, 3 * a8};
         if (!wave_maps) return 1;
         r[1] = {3 * a8 + a4, align_up(4ull * WAVES_PER_WG * n, 256)};
