@@ -31,6 +31,12 @@ const u64 kMaxDynLds = 156 << 10;  // dynamic LDS per workgroup (160 KB per work
 #define LDS_MAP_BUDGET (76u << 10)
 #endif
 const u64 kLdsMapBudget = LDS_MAP_BUDGET;
+// batches whose graphs have at most this many vertices peel in LDS (16
+// bytes per vertex and workgroup)
+#ifndef PEEL_LDS_MAX
+#define PEEL_LDS_MAX 4096
+#endif
+const u32 kPeelLdsMax = PEEL_LDS_MAX;
 const u32 kRelabelSortWg = 64;     // workgroups sorting the long rows of a relabelled CSR
 thread_local float g_phase_ms[kMaxPhases];
 thread_local const char *g_phase_name[kMaxPhases];
@@ -415,6 +421,9 @@ int zero_u64(void *p, u64 n64, hipStream_t s) {
 
 // Phase 1: validation, peeling, orientation and triangle counting.  Leaves
 // ntri and the degeneracy in *hs.
+int orient_and_count(const u32 *rp, const u32 *ci, u32 n, u64 m, void *ws, const Layout &L,
+                     hipStream_t s, DevState *hs, Timer &tm, Plan *pl);
+
 int run_phase1(const u32 *rp, const u32 *ci, u32 n, u64 m, const u64 *vptr, u32 B, void *ws,
                const Layout &L, hipStream_t s, DevState *hs, Timer &tm, Plan *pl) {
     const bool cap = pl && pl->capture;
@@ -463,7 +472,21 @@ int run_phase1(const u32 *rp, const u32 *ci, u32 n, u64 m, const u64 *vptr, u32 
     tm.mark("validate");
     if (n == 0) return ORB_OK;
 
-    // peeling: launch (step, advance) pairs; check for completion every 32
+    // peeling.  A batch of graphs that fit in LDS peels in one launch, a
+    // workgroup per graph; otherwise (step, advance) pairs are launched, with
+    // a check for completion every 32
+    const u32 gm = cap ? pl->gmax : hs->gmax;
+    if (vptr && gm <= kPeelLdsMax) {
+        const u32 cap_n = gm ? gm : 1;
+        const u32 nwg = B < 4096 ? (B ? B : 1) : 4096;
+        k_peel_graphs<<<nwg, WG, 16ull * cap_n, s>>>(vptr, B, n, rp, ci, deg, cap_n, rnd, st);
+        HCHK(hipGetLastError());
+        if (pl && !cap) pl->peel_groups = 1;
+        if (cap) k_plan_guard<<<1, 64, 0, s>>>(st, 1, 0);
+        k_rank_key<<<grid_for(n, WG), WG, 0, s>>>(rnd, n, key);
+        tm.mark("peel");
+        return orient_and_count(rp, ci, n, m, ws, L, s, hs, tm, pl);
+    }
     k_peel_init<<<grid_for(n, WG), WG, 0, s>>>(deg, n, pdeg, rnd, st);
     HCHK(hipGetLastError());
     const unsigned gs = grid_for((u64)n, WG);
@@ -489,7 +512,21 @@ int run_phase1(const u32 *rp, const u32 *ci, u32 n, u64 m, const u64 *vptr, u32 
     if (cap) k_plan_guard<<<1, 64, 0, s>>>(st, 1, 0);
     k_rank_key<<<grid_for(n, WG), WG, 0, s>>>(rnd, n, key);
     tm.mark("peel");
+    return orient_and_count(rp, ci, n, m, ws, L, s, hs, tm, pl);
+}
 
+// Orientation by the rank keys, out-lists, and the triangle count.
+int orient_and_count(const u32 *rp, const u32 *ci, u32 n, u64 m, void *ws, const Layout &L,
+                     hipStream_t s, DevState *hs, Timer &tm, Plan *pl) {
+    const bool cap = pl && pl->capture;
+    DevState *st = at<DevState>(ws, L.state);
+    u32 *src = at<u32>(ws, L.src);
+    u64 *key = at<u64>(ws, L.key);
+    u32 *outdeg = at<u32>(ws, L.outdeg), *outnbr = at<u32>(ws, L.outnbr),
+        *outslot = at<u32>(ws, L.outslot), *tcnt = at<u32>(ws, L.tcnt);
+    u64 *outptr = at<u64>(ws, L.outptr), *triptr = at<u64>(ws, L.triptr),
+        *bsum = at<u64>(ws, L.bsum);
+    int rc = ORB_OK;
     k_outdeg<<<grid_waves(n), WG, 0, s>>>(rp, ci, key, n, outdeg);
     rc = scan<u32>(outdeg, n, outptr, bsum, st, s);
     if (rc) return rc;

@@ -154,6 +154,98 @@ __global__ void k_peel_advance(DevState *st) {
     st->cur = nxt;
 }
 
+// Batched input of small graphs: the same peeling, one workgroup per graph
+// with the graph's remaining degrees, rounds and frontiers in LDS, so the
+// whole batch peels in one launch instead of a launch pair per round.
+// Rounds are numbered within each graph (edges never join two graphs, so
+// only ranks within a graph are compared).  cap: the largest graph the
+// launch's LDS holds; a larger one records an error.  Every loop ends: a
+// pass removes a vertex, or raises the level (and the next pass removes
+// one), or empties a frontier that an earlier pass filled -- at most 3 n
+// passes for a graph of n vertices.
+__global__ void __launch_bounds__(WG) k_peel_graphs(const u64 *vptr, u32 B, u32 n,
+                                                    const u32 *rp, const u32 *ci,
+                                                    const u32 *deg, u32 cap, u32 *rnd,
+                                                    DevState *st) {
+    extern __shared__ u32 pl_lds[];
+    int *pd = (int *)pl_lds;           // remaining degree   [cap]
+    u32 *rr = pl_lds + cap;            // round, or UNSET     [cap]
+    u32 *fr = pl_lds + 2 * cap;        // frontiers           [2 cap]
+    __shared__ u32 sh_fs[2], sh_min;
+    if (st->err) return;
+    for (u64 g = blockIdx.x; g < B; g += gridDim.x) {
+        const u64 lo = vptr[g], hi = vptr[g + 1];
+        if (hi <= lo) continue;
+        if (hi > n || hi - lo > cap) {
+            if (threadIdx.x == 0) atomicOr(&st->err, ERRB_INTERNAL);
+            continue;
+        }
+        const u32 ng = (u32)(hi - lo);
+        for (u32 i = threadIdx.x; i < ng; i += WG) {
+            pd[i] = (int)deg[lo + i];
+            rr[i] = UNSET;
+        }
+        if (threadIdx.x == 0) { sh_fs[0] = 0; sh_fs[1] = 0; }
+        __syncthreads();
+        u32 alive = ng, round = 0, level = 0, maxlevel = 0, cur = 0;
+        for (u32 pass = 0; alive > 0; pass++) {
+            if (pass > 4 * ng + 4) {  // cannot happen (see above)
+                if (threadIdx.x == 0) atomicOr(&st->err, ERRB_INTERNAL);
+                break;
+            }
+            const u32 nxt = cur ^ 1u;
+            const u32 fs = sh_fs[cur];
+            if (threadIdx.x == 0) sh_min = UNSET;
+            __syncthreads();
+            if (fs == 0) {  // scan for alive vertices of remaining degree <= level
+                for (u32 i = threadIdx.x; i < ng; i += WG) {
+                    if (rr[i] != UNSET) continue;
+                    const int d = pd[i];
+                    if (d <= (int)level) {
+                        rr[i] = round;
+                        fr[nxt * cap + atomicAdd(&sh_fs[nxt], 1u)] = i;
+                    } else {
+                        atomicMin(&sh_min, (u32)d);
+                    }
+                }
+            } else {  // remove the frontier; append neighbours dropping to level
+                for (u32 t = threadIdx.x; t < fs; t += WG) {
+                    const u32 v = fr[cur * cap + t];
+                    for (u32 s = rp[lo + v]; s < rp[lo + v + 1]; s++) {
+                        const u32 w = ci[s] - (u32)lo;
+                        if (w >= ng) {  // an edge leaving the graph (rejected earlier)
+                            atomicOr(&st->err, ERRB_INTERNAL);
+                            continue;
+                        }
+                        if (rr[w] != UNSET) continue;
+                        if (atomicSub(&pd[w], 1) == (int)level + 1) {
+                            rr[w] = round;
+                            fr[nxt * cap + atomicAdd(&sh_fs[nxt], 1u)] = w;
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            const u32 nf = sh_fs[nxt];
+            if (nf > 0) {
+                if (level > maxlevel) maxlevel = level;
+                round++;
+                alive -= nf;
+            } else if (fs == 0) {  // an empty scan: jump to the smallest remaining degree
+                u32 nl = level + 1;
+                if (sh_min != UNSET && sh_min > nl) nl = sh_min;
+                level = nl;
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) sh_fs[cur] = 0;
+            cur = nxt;
+        }
+        for (u32 i = threadIdx.x; i < ng; i += WG) rnd[lo + i] = rr[i];
+        if (threadIdx.x == 0) atomicMax(&st->maxlevel, maxlevel);
+        __syncthreads();
+    }
+}
+
 // key[u] = (round << 32) | u : the total order used to orient edges
 __global__ void k_rank_key(const u32 *rnd, u32 n, u64 *key) {
     for (u64 u = GTID; u < n; u += GSTRIDE) key[u] = ((u64)rnd[u] << 32) | u;
