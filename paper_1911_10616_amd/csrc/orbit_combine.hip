@@ -281,9 +281,9 @@ __global__ void k_vert2(const u32 *rp, const u32 *ci, const u32 *deg, const u64 
 // Induced counts: I = Ainv N per row, block by block; Ainv is unit upper
 // triangular, so row i only reads columns >= i and can be overwritten in
 // increasing order.  One wave per tile of 64 rows: the rows are read into
-// LDS with coalesced loads, each lane transforms one row there (a row's
-// 73 words are 584 bytes apart from the next lane's, so the LDS reads are
-// spread over all banks), and the first K columns go out with coalesced
+// LDS with coalesced loads, each lane transforms one row in registers (a
+// row's 73 words are 584 bytes apart from the next lane's, so the LDS reads
+// are spread over all banks), and the first K columns go out with coalesced
 // stores (out may alias ni when K == 73).
 #define XF_ROWS 64
 // With a relabelling, row r of ni belongs to vertex orig[r] of the caller's
@@ -298,13 +298,24 @@ __global__ void __launch_bounds__(WAVE) k_transform(u64 *ni, u32 n, int K, int i
         for (u32 i = lane; i < rows * ORB_NORB; i += WAVE) tile[i] = src[i];
         __syncthreads();
         if (induced && lane < rows) {
-            u64 *R = tile + (u64)lane * ORB_NORB;
-            for (int i = 0; i < K; i++) {
-                u64 acc = 0;
-                for (int k = ORB_AINV_PTR[i]; k < ORB_AINV_PTR[i + 1]; k++)
-                    acc += (u64)(i64)ORB_AINV_VAL[k] * R[ORB_AINV_COL[k]];
-                R[i] = acc;
+            // the row in registers: with both loops unrolled every column
+            // index and coefficient of the table is a constant
+            u64 *T = tile + (u64)lane * ORB_NORB;
+            u64 R[ORB_NORB];
+#pragma unroll
+            for (int c = 0; c < ORB_NORB; c++) R[c] = T[c];
+#pragma unroll
+            for (int i = 0; i < ORB_NORB; i++) {
+                if (i < K) {
+                    u64 acc = 0;
+#pragma unroll
+                    for (int k = ORB_AINV_PTR[i]; k < ORB_AINV_PTR[i + 1]; k++)
+                        acc += (u64)(i64)ORB_AINV_VAL[k] * R[ORB_AINV_COL[k]];
+                    R[i] = acc;
+                }
             }
+#pragma unroll
+            for (int c = 0; c < ORB_NORB; c++) T[c] = R[c];
         }
         __syncthreads();
         u64 *dst = out + base * K;
