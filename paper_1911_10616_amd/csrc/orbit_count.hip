@@ -896,6 +896,8 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
     __shared__ u32 sh_hub[WG], sh_nhub;  // workgroup groups: this chunk's arcs to hubs
     __shared__ FlatLds sh_flat[WAVES_PER_WG];
     FlatLds &FL = sh_flat[wave_in_wg()];
+    // per-arc centre sums of the flat walk (wave groups only)
+    __shared__ u64 sh_cen[kWaveGroups ? WAVES_PER_WG : 1][2][WAVE];
     // dynamic LDS: per-wave wheel maps of kl positions (u32) and touched
     // lists (u16), kl <= PAIR_KMAP_LDS; in workgroup groups the same bytes
     // also serve as one map of hmax = 6 kl positions for the hub arcs
@@ -944,8 +946,38 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
         GP::sync();
         if (pass_cycles) pass_mark(pass_cycles, 0, t_pass);
         // wedges a - y - b, b > a: s and ta of the pair (a, b); UNR entries
-        // per lane per step, whose loads and atomics are independent
-        wave_loop(&sh_next, da, [&](u32 iy) {
+        // per lane per step, whose loads and atomics are independent.  A
+        // wave with a light source (d(a) <= 64) walks all its arcs' lists
+        // at once, one list per lane, instead of one arc after another.
+        const bool flat = kWaveGroups && da <= WAVE;
+        if (flat) {
+            u32 cnt = 0;
+            if (lane < da) {
+                const u32 y = ci[ba + lane];
+                const u32 by = rp[y], ey = rp[y + 1];
+                const u32 st0 = by + lbound(ci + by, ey - by, a + 1);
+                cnt = ey - st0;
+                FL.ptr[lane] = st0;
+                FL.aux[lane] = T[ba + lane];
+            }
+            flat_walk(FL, cnt, [&](const u32 *jv, const u32 *ov, const bool *ok) {
+                u32 bv[UNR];
+                u64 old[UNR];
+#pragma unroll
+                for (int k = 0; k < UNR; k++) bv[k] = ok[k] ? ci[(u32)FL.ptr[jv[k]] + ov[k]] : UNSET;
+#pragma unroll
+                for (int k = 0; k < UNR; k++)
+                    if (bv[k] != UNSET)
+                        old[k] = atomicAdd(&P.s(bv[k] - vb), (1ull << PS_SHIFT) | FL.aux[jv[k]]);
+#pragma unroll
+                for (int k = 0; k < UNR; k++)
+                    if (bv[k] != UNSET) {
+                        nsteps++;
+                        if (((old[k] & ~PS_ADJ) >> PS_SHIFT) == 0)
+                            P.touched[atomicAdd(&sh_nt, 1u)] = bv[k];
+                    }
+            });
+        } else wave_loop(&sh_next, da, [&](u32 iy) {
             const u32 say = ba + iy, y = ci[say];
             const u64 tay = T[say];
             const u32 by = rp[y], ey = rp[y + 1];
@@ -1189,8 +1221,53 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
         }
         GP::sync();
         if (pass_cycles) pass_mark(pass_cycles, 3, t_pass);
-        // centre terms, and a's tb (s-1) wedge by wedge
-        wave_loop(&sh_next, da, [&](u32 iy) {
+        // centre terms, and a's tb (s-1) wedge by wedge (light sources of
+        // wave groups: all arcs at once, per-arc sums in LDS)
+        if (flat) {
+            u32 cnt = 0;
+            u64 *c49 = sh_cen[wave_in_wg()][0], *c62 = sh_cen[wave_in_wg()][1];
+            c49[lane] = 0;
+            c62[lane] = 0;
+            if (lane < da) {
+                const u32 y = ci[ba + lane];
+                const u32 by = rp[y], ey = rp[y + 1];
+                const u32 st0 = by + lbound(ci + by, ey - by, a + 1);
+                cnt = ey - st0;
+                FL.ptr[lane] = st0;
+            }
+            flat_walk(FL, cnt, [&](const u32 *jv, const u32 *ov, const bool *ok) {
+                u32 bv[UNR];
+                u64 tv[UNR], sv[UNR], ev2[UNR];
+#pragma unroll
+                for (int k = 0; k < UNR; k++) {
+                    const u32 s = ok[k] ? (u32)FL.ptr[jv[k]] + ov[k] : 0;
+                    bv[k] = ok[k] ? ci[s] : UNSET;
+                    tv[k] = ok[k] ? T[s] : 0;
+                }
+#pragma unroll
+                for (int k = 0; k < UNR; k++)
+                    if (bv[k] != UNSET) {
+                        sv[k] = P.s(bv[k] - vb);
+                        ev2[k] = P.e(bv[k] - vb);
+                    }
+#pragma unroll
+                for (int k = 0; k < UNR; k++) {
+                    if (bv[k] == UNSET) continue;
+                    const u64 sb = ps_s(sv[k], wide);
+                    nsteps++;
+                    if (sb >= 2) {
+                        atomicAdd(&c49[jv[k]], c2((i64)sb - 1));
+                        atomicAdd(&c62[jv[k]], ev2[k] >> 1);
+                        l51 += tv[k] * (sb - 1);
+                    }
+                }
+            });
+            if (lane < da) {
+                const u32 y = ci[ba + lane];
+                atomic_add_u64(&VACC(y, VA_49), c49[lane]);
+                atomic_add_u64(&VACC(y, VA_62), c62[lane]);
+            }
+        } else wave_loop(&sh_next, da, [&](u32 iy) {
             const u32 say = ba + iy, y = ci[say];
             const u32 by = rp[y], ey = rp[y + 1];
             const u32 st0 = by + lbound(ci + by, ey - by, a + 1);
