@@ -1350,6 +1350,12 @@ struct C5Scratch {
     u64 *P, *CI, *TO, *SW;
     unsigned char *mark;
 };
+// Per-list values and sums of a wave's flat walks over a light source's
+// lists (wave groups).
+struct C5Flat {
+    u64 acc[WAVE], acc2[WAVE], kw[WAVE];
+    u32 tin[WAVE], cnt[WAVE];
+};
 // Layout (each array 256-aligned): Wm, P, CI | touched | mark | C, TO, SW | jt.
 // The first, third and fourth groups must be zero when a source starts.
 __device__ inline C5Scratch c5_scratch(unsigned char *base, u32 n) {
@@ -1384,6 +1390,14 @@ __global__ void __launch_bounds__(WG) k_c5(const u32 *rp, const u32 *ci, const u
     __shared__ u64 sh_red[WAVES_PER_WG];
     C5Scratch C = c5_scratch(scratch + GP::global_id() * stride, mapn);
     const u32 lane = lane_id();
+    // light sources of wave groups walk all their lists at once (one list
+    // per lane, flat), with per-list values and sums in LDS
+    constexpr bool kWaveGroups = GP::per_wg > 1;
+    constexpr u32 kF = kWaveGroups ? WAVES_PER_WG : 1;
+    __shared__ FlatLds sh_flat[kF];
+    __shared__ C5Flat sh_c5f[kF];
+    FlatLds &FL = sh_flat[kWaveGroups ? wave_in_wg() : 0];
+    C5Flat &F = sh_c5f[kWaveGroups ? wave_in_wg() : 0];
     for (;;) {
         const u32 l = next_source<GP>(work, sh_q, order, n, st);
         if (l >= n) break;
@@ -1392,13 +1406,60 @@ __global__ void __launch_bounds__(WG) k_c5(const u32 *rp, const u32 *ci, const u
         if (dl < 2) continue;
         const u64 kl = key[l];
         u64 nsteps = 0;  // loop iterations of this thread for this source
+        const bool flat = kWaveGroups && dl <= WAVE;
         for (u32 i = GP::rank(); i < dl; i += GP::size) C.mark[ci[bl + i] - vb] = 1;
         if (GP::rank() == 0) { sh_nt = 0; sh_nj = 0; sh_next = 0; }
         GP::sync();
         // pass 1: non-in-in wedges l - w - i; for every in-neighbour k of l,
         // each out-arc k -> x (x != l): c(x), the Tout part of x's credit,
         // and the Tmid part of CI(x)
-        wave_loop(&sh_next, dl, [&](u32 iw) {
+        if (flat) {
+            u32 w = 0, cnt = 0;
+            u64 kw = 0;
+            if (lane < dl) {  // the wedge ends of w: N+(w) if l -> w, else N(w)
+                w = ci[bl + lane];
+                kw = key[w];
+                const u64 b = kw > kl ? out_ptr[w] : rp[w];
+                cnt = (u32)((kw > kl ? out_ptr[w + 1] : (u64)rp[w + 1]) - b);
+                FL.ptr[lane] = (u64)((kw > kl ? out_nbr : ci) + b);
+            }
+            flat_walk(FL, cnt, [&](const u32 *jv, const u32 *ov, const bool *ok) {
+                u32 iv[UNR];
+#pragma unroll
+                for (int k = 0; k < UNR; k++) iv[k] = ok[k] ? ((const u32 *)FL.ptr[jv[k]])[ov[k]] : l;
+#pragma unroll
+                for (int k = 0; k < UNR; k++)
+                    if (ok[k]) {
+                        nsteps++;
+                        if (iv[k] != l) atomicAdd(&C.Wm[iv[k] - vb], 1u);
+                    }
+            });
+            cnt = 0;
+            if (lane < dl && kw < kl) {  // w -> l: w plays k, its out-arcs k -> x
+                cnt = (u32)(out_ptr[w + 1] - out_ptr[w]);
+                FL.ptr[lane] = out_ptr[w];
+            }
+            flat_walk(FL, cnt, [&](const u32 *jv, const u32 *ov, const bool *ok) {
+#pragma unroll
+                for (int k = 0; k < UNR; k++) {
+                    if (!ok[k]) continue;
+                    const u64 q = FL.ptr[jv[k]] + ov[k];
+                    const u32 x = out_nbr[q];
+                    nsteps++;
+                    if (x == l) continue;
+                    const u32 sq = out_slot[q];
+                    const u32 ts = T[sq], ti = Tin[sq], tm = Tmid[sq];
+                    const bool adj = C.mark[x - vb] != 0;
+                    const u64 kx = key[x];
+                    const u32 xl = adj && kx < kl, lx = adj && kx > kl;  // x -> l, l -> x
+                    if (atomicAdd(&C.C[x - vb], 1u) == 0) C.jt[atomicAdd(&sh_nj, 1u)] = x;
+                    const u64 to = (u64)(ts - ti - tm) - xl;
+                    if (to) atomicAdd(&C.TO[x - vb], to);
+                    const u64 cm = (u64)tm - lx;
+                    if (cm) atomicAdd(&C.CI[x - vb], cm);
+                }
+            });
+        } else wave_loop(&sh_next, dl, [&](u32 iw) {
             const u32 w = ci[bl + iw];
             if (key[w] > kl) {  // l -> w, then w -> i
                 for (u64 q = out_ptr[w] + lane; q < out_ptr[w + 1]; q += WAVE) {
@@ -1436,7 +1497,45 @@ __global__ void __launch_bounds__(WG) k_c5(const u32 *rp, const u32 *ci, const u
         // pass 1b: every middle vertex j reached: P(i) += c(j) and
         // CI(i) += c(j) [j~l] for i in N+(j) \ {l}; SW(j); credit of j
         const u32 nj = sh_nj;
-        wave_loop(&sh_next, nj, [&](u32 t) {
+        if (flat) {  // 64 middle vertices at a time, one out-list per lane
+            for (u32 t0 = 0; t0 < nj; t0 += WAVE) {
+                const u32 t = t0 + lane;
+                u32 j = 0, cnt = 0;
+                u64 cj = 0;
+                bool mj = false;
+                F.acc[lane] = 0;
+                F.cnt[lane] = 0;
+                if (t < nj) {
+                    j = C.jt[t];
+                    cj = C.C[j - vb];
+                    mj = C.mark[j - vb] != 0;
+                    FL.ptr[lane] = out_ptr[j];
+                    FL.aux[lane] = (u32)cj | (mj ? 0x80000000u : 0u);  // c(j) <= d(l) < 2^31
+                    cnt = (u32)(out_ptr[j + 1] - out_ptr[j]);
+                }
+                flat_walk(FL, cnt, [&](const u32 *jv, const u32 *ov, const bool *ok) {
+#pragma unroll
+                    for (int k = 0; k < UNR; k++) {
+                        if (!ok[k]) continue;
+                        const u32 i = out_nbr[FL.ptr[jv[k]] + ov[k]];
+                        nsteps++;
+                        if (i == l) continue;
+                        const u32 aux = FL.aux[jv[k]];
+                        const u64 cjk = aux & 0x7fffffffu;
+                        if (atomicAdd(&C.P[i - vb], cjk) == 0) C.touched[atomicAdd(&sh_nt, 1u)] = i;
+                        if (aux >> 31) atomicAdd(&C.CI[i - vb], cjk);
+                        atomicAdd(&F.acc[jv[k]], (u64)C.Wm[i - vb]);
+                        atomicAdd(&F.cnt[jv[k]], 1u);
+                    }
+                });
+                if (t < nj) {
+                    const u64 sw = F.acc[lane], dj = F.cnt[lane];
+                    C.SW[j - vb] = sw;
+                    atomic_add_u64(&cacc[j], cj * (sw - (mj ? dj : 0)) - C.TO[j - vb]);
+                }
+                wave_sync();
+            }
+        } else wave_loop(&sh_next, nj, [&](u32 t) {
             const u32 j = C.jt[t];
             const u64 cj = C.C[j - vb];
             const bool mj = C.mark[j - vb] != 0;
@@ -1461,7 +1560,67 @@ __global__ void __launch_bounds__(WG) k_c5(const u32 *rp, const u32 *ci, const u
         if (GP::rank() == 0) sh_next = 0;
         GP::sync();
         // pass 2: credits of w per wedge, and of k per out-arc k -> j
-        wave_loop(&sh_next, dl, [&](u32 iw) {
+        if (flat) {
+            u32 w = 0, cnt = 0;
+            u64 kw = 0;
+            F.acc[lane] = 0;
+            F.acc2[lane] = 0;
+            if (lane < dl) {  // the wedge ends of w, as in pass 1
+                w = ci[bl + lane];
+                kw = key[w];
+                F.kw[lane] = kw;
+                F.tin[lane] = Tin[bl + lane];
+                FL.aux[lane] = kw > kl;
+                FL.ptr[lane] = kw > kl ? out_ptr[w] : (u64)rp[w];
+                cnt = (u32)((kw > kl ? out_ptr[w + 1] : (u64)rp[w + 1]) - FL.ptr[lane]);
+            }
+            flat_walk(FL, cnt, [&](const u32 *jv, const u32 *ov, const bool *ok) {
+#pragma unroll
+                for (int k = 0; k < UNR; k++) {
+                    if (!ok[k]) continue;
+                    const u32 pj = jv[k];
+                    const u64 idx = FL.ptr[pj] + ov[k];
+                    const u64 tin = F.tin[pj];
+                    if (FL.aux[pj]) {  // l -> w -> i
+                        const u64 p = C.P[out_nbr[idx] - vb];
+                        if (p) atomicAdd(&F.acc[pj], p - tin);
+                    } else {  // w -> l
+                        const u32 i = ci[idx];
+                        if (i == l) continue;
+                        const u64 p = C.P[i - vb];
+                        if (!p) continue;
+                        u64 corr = 0;
+                        const u64 ki = key[i];
+                        if (ki > F.kw[pj]) {  // w -> i
+                            const bool li = C.mark[i - vb] && ki > kl;  // l -> i
+                            corr = tin + (u64)Tmid[idx] - (li ? 1 : 0);
+                        }
+                        atomicAdd(&F.acc[pj], p - corr);
+                    }
+                }
+            });
+            cnt = 0;
+            if (lane < dl && kw < kl) {  // w plays k: its out-arcs k -> j, j != l
+                cnt = (u32)(out_ptr[w + 1] - out_ptr[w]);
+                FL.ptr[lane] = out_ptr[w];
+            }
+            flat_walk(FL, cnt, [&](const u32 *jv, const u32 *ov, const bool *ok) {
+#pragma unroll
+                for (int k = 0; k < UNR; k++) {
+                    if (!ok[k]) continue;
+                    const u64 q = FL.ptr[jv[k]] + ov[k];
+                    const u32 j = out_nbr[q];
+                    if (j == l) continue;
+                    const u32 sq = out_slot[q];
+                    const bool mj = C.mark[j - vb] != 0;
+                    const u32 jl = mj && key[j] < kl;  // j -> l
+                    const u64 dj = (out_ptr[j + 1] - out_ptr[j]) - jl;
+                    const u64 tout = (u64)T[sq] - Tin[sq] - Tmid[sq];
+                    atomicAdd(&F.acc2[jv[k]], C.SW[j - vb] - (mj ? dj : 0) - tout + jl);
+                }
+            });
+            if (lane < dl) atomic_add_u64(&cacc[w], F.acc[lane] + F.acc2[lane]);
+        } else wave_loop(&sh_next, dl, [&](u32 iw) {
             const u32 slw = bl + iw;
             const u32 w = ci[slw];
             const u64 kw = key[w];
@@ -1536,7 +1695,21 @@ __global__ void __launch_bounds__(WG) k_c5(const u32 *rp, const u32 *ci, const u
         }
         if (GP::rank() == 0) sh_next = 0;
         GP::sync();
-        wave_loop(&sh_next, dl, [&](u32 iw) {
+        if (flat) {
+            u32 cnt = 0;
+            if (lane < dl) {
+                const u32 w = ci[bl + lane];
+                const bool lw = key[w] > kl;
+                const u64 b = lw ? out_ptr[w] : rp[w];
+                cnt = (u32)((lw ? out_ptr[w + 1] : (u64)rp[w + 1]) - b);
+                FL.ptr[lane] = (u64)((lw ? out_nbr : ci) + b);
+            }
+            flat_walk(FL, cnt, [&](const u32 *jv, const u32 *ov, const bool *ok) {
+#pragma unroll
+                for (int k = 0; k < UNR; k++)
+                    if (ok[k]) C.Wm[((const u32 *)FL.ptr[jv[k]])[ov[k]] - vb] = 0;
+            });
+        } else wave_loop(&sh_next, dl, [&](u32 iw) {
             const u32 w = ci[bl + iw];
             if (key[w] > kl) {
                 for (u64 q = out_ptr[w] + lane; q < out_ptr[w + 1]; q += WAVE) C.Wm[out_nbr[q] - vb] = 0;
