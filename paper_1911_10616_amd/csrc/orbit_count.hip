@@ -896,8 +896,9 @@ __global__ void __launch_bounds__(WG) k_pairs(const u32 *rp, const u32 *ci, cons
     __shared__ u32 sh_hub[WG], sh_nhub;  // workgroup groups: this chunk's arcs to hubs
     __shared__ FlatLds sh_flat[WAVES_PER_WG];
     FlatLds &FL = sh_flat[wave_in_wg()];
-    // per-arc centre sums of the flat walk (wave groups only)
-    __shared__ u64 sh_cen[kWaveGroups ? WAVES_PER_WG : 1][2][WAVE];
+    // per-arc centre sums of the flat walk (wave groups only; a token size
+    // otherwise: three workgroups of hub wheel maps fill a CU's LDS)
+    __shared__ u64 sh_cen[kWaveGroups ? WAVES_PER_WG : 1][2][kWaveGroups ? WAVE : 1];
     // dynamic LDS: per-wave wheel maps of kl positions (u32) and touched
     // lists (u16), kl <= PAIR_KMAP_LDS; in workgroup groups the same bytes
     // also serve as one map of hmax = 6 kl positions for the hub arcs
