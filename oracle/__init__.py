@@ -44,7 +44,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with gcc (OpenMP over roots)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-fPIC", "-fopenmp", "-shared", "-o", tmp, _SRC])
+        subprocess.check_call(["gcc", "-O2", "-fPIC", "-fopenmp", "-pthread", "-shared", "-o", tmp, _SRC])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -52,7 +52,7 @@ def build(force: bool = True) -> str:
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
             build()
         lib = ctypes.CDLL(_LIB)
         u32p = ctypes.POINTER(ctypes.c_uint32)

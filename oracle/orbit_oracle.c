@@ -44,6 +44,7 @@
 #include <string.h>
 #ifdef _OPENMP
 #include <omp.h>
+#include <pthread.h>
 #endif
 
 #define NORB 73
@@ -106,7 +107,6 @@ static const int EDGE_LABELS[NEORB][3] = {
 };
 
 /* ---- derived tables ---------------------------------------------------- */
-static int g_ready = 0;
 static int g_status = 0;               /* 0 ok; <0 transcription inconsistent */
 static int g_node_orbit[NGRAPHLET][MAXK];
 static int g_aut[NGRAPHLET];
@@ -257,11 +257,13 @@ static void build_tables(void) {
     }
     for (int o = 0; o < NORB; o++) if (g_orbit_graphlet[o] < 0) g_status = -6;
     build_edge_tables();
-    g_ready = 1;
 }
 
+/* The tables are built once, also when several host threads make their
+ * first call at the same time. */
+static pthread_once_t g_once = PTHREAD_ONCE_INIT;
 static void ensure_tables(void) {
-    if (!g_ready) build_tables();
+    pthread_once(&g_once, build_tables);
 }
 
 /* ---- graph access ------------------------------------------------------ */

@@ -453,3 +453,33 @@ def test_edge_orbits_complete_and_cycle(n):
         rp, ci = gg.cycle(n)
         exp = [1, 0, 1, 1] + [0] * 8
         assert (oracle.edge_counts(rp, ci).astype(np.int64) == np.array(exp)).all()
+
+
+def test_first_calls_from_many_threads():
+    """The oracle's tables are built once even when several host threads make
+    their first call together (the CPU baseline calls it from a pool)."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "from concurrent.futures import ThreadPoolExecutor\n"
+        "import numpy as np, oracle\n"
+        "from paper_1911_10616_amd import graphgen as gg\n"
+        "rp, ci = gg.erdos_renyi(30, 0.3, 5)\n"
+        "import threading\n"
+        "oracle._load()\n"
+        "go = threading.Barrier(16)\n"
+        "def one(v):\n"
+        "    if v < 16: go.wait()\n"
+        "    out, comp = oracle.rooted_counts(rp, ci, [v], kmax=5, threads=1)\n"
+        "    return out[0]\n"
+        "with ThreadPoolExecutor(16) as ex:\n"
+        "    rows = list(ex.map(one, range(30)))\n"
+        "full = oracle.induced_counts(rp, ci)\n"
+        "assert np.array_equal(np.stack(rows), full)\n"
+        "print('ok')\n" % root)
+    for _ in range(5):  # fresh processes: the tables are not built yet
+        r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
+                           timeout=120)
+        assert r.returncode == 0 and r.stdout.strip() == "ok", r.stderr[-2000:]
