@@ -66,8 +66,10 @@ extern "C" {
 #define ORB_E_INTERNAL (-9)     /* internal consistency check failed */
 #define ORB_E_BATCH (-10)       /* batched input: graph offsets not 0..n and non-decreasing,
                                    or an edge joining two graphs */
-#define ORB_E_TOO_LARGE (-11)   /* orbit_count_noalloc: the count needs more memory than its
-                                   static buffer (orbit_noalloc_capacity()) holds */
+#define ORB_E_TOO_LARGE (-11)   /* the count needs more memory than there is: more than the
+                                   static buffer of orbit_count_noalloc
+                                   (orbit_noalloc_capacity()), or, for orbit_count, a
+                                   workspace larger than the device's free memory */
 
 /* option flags */
 #define ORB_NONINDUCED 0x1u /* return non-induced counts DM(u, theta) */
@@ -148,7 +150,8 @@ typedef struct orb_opts {
 int orbit_num_orbits(int k_max);
 
 /* Minimal form: counts for every vertex, default options, null stream.
- * Allocates its workspace with hipMalloc and frees it before returning.
+ * Allocates its workspace with hipMalloc and frees it before returning;
+ * ORB_E_TOO_LARGE when that workspace exceeds the device's free memory.
  * m = number of undirected edges (col_idx has 2m entries). */
 int orbit_count(const uint32_t *row_ptr, const uint32_t *col_idx, uint32_t n, uint64_t m,
                 int k_max, uint64_t *counts);

@@ -1118,6 +1118,11 @@ int orbit_count(const uint32_t *row_ptr, const uint32_t *col_idx, uint32_t n, ui
     uint64_t need = 0;
     int rc = orbit_workspace_query(row_ptr, col_idx, n, m, k_max, nullptr, nullptr, &need);
     if (rc) return rc;
+    // a workspace beyond the device's free memory is a size limit, not a
+    // failed call (R-MAT scale 24 with edge factor 32 needs more than 288 GB)
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return ORB_E_DEVICE;
+    if (need > free_b) return ORB_E_TOO_LARGE;
     void *ws = nullptr;
     if (hipMalloc(&ws, need ? need : 256) != hipSuccess) return ORB_E_DEVICE;
     rc = orbit_count_ex(row_ptr, col_idx, n, m, k_max, counts, nullptr, ws, need, nullptr,
@@ -1349,7 +1354,8 @@ const char *orbit_strerror(int status) {
         case ORB_E_INTERNAL: return "internal consistency check failed";
         case ORB_E_BATCH: return "batched input: bad graph offsets or an edge joining two graphs";
         case ORB_E_TOO_LARGE:
-            return "graph needs more device memory than orbit_count_noalloc's static buffer holds";
+            return "graph needs more device memory than there is (orbit_count_noalloc's static "
+                   "buffer, or the device's free memory for orbit_count)";
         default: return "unknown status";
     }
 }
