@@ -90,9 +90,10 @@ extern "C" {
                                orbit_count_status.  Not with ORB_TIMING. */
 #define ORB_SERIAL_GROUPS 0x8u /* k_max = 5: run the three independent orbit groups
                                (pair sweep, 5-cycles, second clique pass) one after
-                               another on `stream` instead of overlapping them on two
-                               helper streams (section "Runtime distribution and
-                               parallel speedup" runs these groups in parallel) */
+                               another on `stream` instead of running the last two on
+                               a helper stream beside the pair sweep (section "Runtime
+                               distribution and parallel speedup" runs these groups in
+                               parallel) */
 
 /* order in which the per-source kernels take their sources (the counts
  * are the same under every schedule; only the work balance changes) */

@@ -1084,7 +1084,7 @@ int orbit_count_noalloc(const uint32_t *row_ptr, const uint32_t *col_idx, uint32
     orb_opts o;
     memset(&o, 0, sizeof o);
     o.num_wg = nwg;
-    o.flags = ORB_SERIAL_GROUPS;  // one stream: no helper streams are created
+    o.flags = ORB_SERIAL_GROUPS;  // one stream: no helper stream is created
     return count_impl(row_ptr, col_idx, n, m, nullptr, 0, k_max, (u64 *)counts, nullptr, nullptr, ws,
                       ORB_NOALLOC_BYTES, nullptr, s, &o, false);
 }

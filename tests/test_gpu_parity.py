@@ -275,8 +275,9 @@ def test_relabel_argument_errors(orbit):
 
 @pytest.mark.parametrize("groups", ["wg", "wave"])
 def test_orbit_groups_serial_and_overlapped(orbit, groups):
-    """The three 5-vertex orbit groups overlapped on helper streams (the
-    default) or run one after another give the oracle's counts."""
+    """The three 5-vertex orbit groups overlapped (the default: two of them
+    on a helper stream beside the pair sweep) or run one after another give
+    the oracle's counts."""
     graphs = [gg.erdos_renyi(40, 0.3, 8101), gg.barabasi_albert(200, 3, 8102),
               gg.chung_lu(500, 8.0, 2.1, 80.0, 2000, 8103), gg.complete(12)]
     for i, (rp, ci) in enumerate(graphs):
