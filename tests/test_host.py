@@ -68,3 +68,34 @@ def test_orbit_tables_match_oracle():
     t = oracle.tables()
     assert list(pat) == [int(x) for x in t["orbit_graphlet"]]
     assert list(size) == [int(x) for x in t["orbit_size"]]
+
+
+def test_every_status_has_a_message():
+    from paper_1911_10616_amd import orbit
+    msgs = [orbit._lib.orbit_strerror(c).decode() for c in range(0, -12, -1)]
+    assert all(m and m != "unknown status" for m in msgs), msgs
+    assert len(set(msgs)) == len(msgs)
+    assert orbit._lib.orbit_strerror(-12).decode() == "unknown status"
+
+
+def test_pattern_counts_and_noalloc_capacity():
+    """Host-only calls: patterns with 2..k vertices (the oracle's tables)
+    and the size of the static buffer of the allocation-free entry."""
+    from paper_1911_10616_amd import orbit
+    t = oracle.tables()
+    k_of = [int(k) for k in t["pattern_k"]]
+    for k in (3, 4, 5):
+        assert orbit._lib.orbit_num_patterns(k) == sum(1 for x in k_of if 2 <= x <= k)
+    assert orbit._lib.orbit_num_patterns(6) == 0
+    orbit._lib.orbit_noalloc_capacity.restype = ctypes.c_uint64
+    assert orbit._lib.orbit_noalloc_capacity() == 64 << 20
+
+
+def test_bench_refuses_several_gpus():
+    """bench.py counts on one GPU; asked for more it says so and fails."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr)
