@@ -253,7 +253,7 @@ def run_batched(args, orbit, gg, rank):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="chunglu1m", choices=sorted(WORKLOADS))
     ap.add_argument("--schedule", default="mlp", choices=("id", "static", "mlp"),
