@@ -72,9 +72,6 @@ def setup():
     rec = {"wall_s": wall, "ws_bytes": c.ws_bytes, "phases_ms": dict(orbit.last_phase_times()),
            "kernels_ms": orbit.last_kernel_times(), "work": orbit.last_stats()}
     print("rmat22 counted", json.dumps(rec), flush=True)
-    os.makedirs("gpurun_out", exist_ok=True)
-    with open(os.path.join("gpurun_out", "rmat22_run.json"), "w") as f:
-        json.dump(rec, f)
     sums, pats, _ = orbit.voc_summary(out, 5)
     counts = out.cpu().numpy().view(U).copy()
     f = flags.cpu().numpy().copy()
